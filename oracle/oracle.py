@@ -1,0 +1,194 @@
+"""FP64 CPU oracle of the tied-array beam former -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The GPU library never calls it and shares
+no code with it.  The arithmetic lives in ``lbf_oracle.c`` (plain C, FP64);
+this file compiles it with gcc and marshals numpy arrays.
+
+Definitions followed (Mol & Romein, "The LOFAR Beam Former"):
+
+* ``delays``     -- tau[b][s] = p_s . (u_b - u_ref) / c0 (Sec. 3; Sec. 4.3:
+  weights depend on station location, channel frequency and beam coordinates)
+* ``weights``    -- w[c][b][s] = exp(-2 pi i frac(f_c tau)) (Sec. 3, phase shift
+  by a complex multiplication per sample)
+* ``beamform``   -- y[c][b][t][p] = sum_s w[c][b][s] x[s][c][t][p] (Sec. 1,
+  Sec. 3, Sec. 4.3: weighted addition of the station signals)
+* ``stokes``     -- I, Q, U, V as defined in Sec. 4.5
+* ``integrate``  -- sums over t_int samples and f_int channels (Sec. 3, Sec. 5.1)
+* ``reorder``    -- final per-beam, per-Stokes order [b][k][t'][c'] (Sec. 4.6)
+* ``incoherent`` -- sum over stations of per-station Stokes (Sec. 3)
+
+Parity pins for every function are in ``tests/test_oracle_pins.py``; the
+absolute values of the beam former have no worked example in the paper, so
+they are pinned by closed forms, invariants, brute force and an independent
+library routine (numpy einsum), not by printed numbers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbf_oracle.c")
+_BUILD = os.path.join(_HERE, "_build")
+_SO = os.path.join(_BUILD, "liboracle.so")
+_XT = {"ci8": 0, "ci16": 1, "cf32": 2}
+_lock = threading.Lock()
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile lbf_oracle.c into _build/liboracle.so with gcc (plain -O2)."""
+    os.makedirs(_BUILD, exist_ok=True)
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp,
+                               _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_SO)
+            vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+            lib.lbfo_delays.argtypes = [_dp, i, _dp, i, vp, _dp]
+            lib.lbfo_weights.argtypes = [_dp, i, i, _dp, i, _dp]
+            lib.lbfo_beamform.argtypes = [vp, i, i, i, i, i, i, _dp, i, _dp]
+            lib.lbfo_stokes.argtypes = [_dp, i, i, i, _dp]
+            lib.lbfo_integrate.argtypes = [_dp, i, i, i, i, i, i, _dp]
+            lib.lbfo_reorder.argtypes = [_dp, i, i, i, i, i, _dp]
+            lib.lbfo_incoherent.argtypes = [vp, i, i, i, i, i, i, i, _dp]
+            lib.lbfo_pipeline.argtypes = [vp, i, i, i, i, _dp, _dp, i, vp, _dp, i, i, i, i, _dp]
+            lib.lbfo_pipeline.restype = i
+            for f in ("lbfo_delays", "lbfo_weights", "lbfo_beamform", "lbfo_stokes", "lbfo_integrate",
+                      "lbfo_reorder", "lbfo_incoherent"):
+                getattr(lib, f).restype = None
+            _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _xtype_of(x: np.ndarray) -> int:
+    if x.dtype == np.int8:
+        return _XT["ci8"]
+    if x.dtype == np.int16:
+        return _XT["ci16"]
+    if x.dtype == np.float32:
+        return _XT["cf32"]
+    raise TypeError("station samples must be int8, int16 or float32, got %s" % x.dtype)
+
+
+def delays(pos, dirs, ref=None) -> np.ndarray:
+    """tau[b][s] in seconds."""
+    pos, dirs = _f64(pos), _f64(dirs)
+    S, B = pos.shape[0], dirs.shape[0]
+    tau = np.empty((B, S))
+    refp = None if ref is None else _f64(ref)
+    _load().lbfo_delays(pos, S, dirs, B, None if refp is None else refp.ctypes.data, tau)
+    return tau
+
+
+def weights(tau, freq) -> np.ndarray:
+    """w[c][b][s] complex128."""
+    tau, freq = _f64(tau), _f64(freq)
+    B, S = tau.shape
+    C = freq.shape[0]
+    w = np.empty((C, B, S, 2))
+    _load().lbfo_weights(tau, B, S, freq, C, w)
+    return w[..., 0] + 1j * w[..., 1]
+
+
+def beamform(x: np.ndarray, w: np.ndarray, c_lo: int = 0, nc: int | None = None) -> np.ndarray:
+    """y[nc][B][T][2] complex128 for channels [c_lo, c_lo+nc) of x[S][C][T][2][2];
+    w holds the weights of those channels only: w[nc][B][S]."""
+    x = np.ascontiguousarray(x)
+    S, C, T = x.shape[:3]
+    if nc is None:
+        nc = C - c_lo
+    B = w.shape[1]
+    wr = np.ascontiguousarray(np.stack([w.real, w.imag], axis=-1), dtype=np.float64)
+    assert wr.shape == (nc, B, S, 2)
+    y = np.empty((nc, B, T, 2, 2))
+    _load().lbfo_beamform(x.ctypes.data, _xtype_of(x), S, C, T, c_lo, nc, wr, B, y)
+    return y[..., 0] + 1j * y[..., 1]
+
+
+def stokes(y: np.ndarray) -> np.ndarray:
+    """st[c][b][t][4] = (I, Q, U, V) float64 from y[c][b][t][2] complex."""
+    C, B, T = y.shape[:3]
+    yr = np.ascontiguousarray(np.stack([y.real, y.imag], axis=-1), dtype=np.float64)
+    st = np.empty((C, B, T, 4))
+    _load().lbfo_stokes(yr, C, B, T, st)
+    return st
+
+
+def integrate(st: np.ndarray, K: int, t_int: int, f_int: int) -> np.ndarray:
+    """s[c'][b][t'][K] (sums)."""
+    C, B, T = st.shape[:3]
+    assert C % f_int == 0 and T % t_int == 0
+    s = np.empty((C // f_int, B, T // t_int, K))
+    _load().lbfo_integrate(_f64(st), C, B, T, K, t_int, f_int, s)
+    return s
+
+
+def reorder(s: np.ndarray) -> np.ndarray:
+    """[c'][b][t'][k] -> [b][k][t'][c'] (real or complex)."""
+    C2, B, T2, K = s.shape
+    if np.iscomplexobj(s):
+        sr = np.ascontiguousarray(np.stack([s.real, s.imag], axis=-1), dtype=np.float64)
+        out = np.empty((B, K, T2, C2, 2))
+        _load().lbfo_reorder(sr, C2, B, T2, K, 2, out)
+        return out[..., 0] + 1j * out[..., 1]
+    out = np.empty((B, K, T2, C2))
+    _load().lbfo_reorder(_f64(s), C2, B, T2, K, 1, out)
+    return out
+
+
+def incoherent(x: np.ndarray, K: int, t_int: int, f_int: int) -> np.ndarray:
+    """Incoherent beam inc[c'][t'][K]: sum over stations of per-station Stokes."""
+    x = np.ascontiguousarray(x)
+    S, C, T = x.shape[:3]
+    inc = np.empty((C // f_int, T // t_int, K))
+    _load().lbfo_incoherent(x.ctypes.data, _xtype_of(x), S, C, T, K, t_int, f_int, inc)
+    return inc
+
+
+def pipeline(x: np.ndarray, pos, dirs, ref, freq, K: int, t_int: int = 1, f_int: int = 1,
+             nthreads: int = 1) -> np.ndarray:
+    """Whole chain: out[B][K][T/t_int][C/f_int] (K in {1, 4}) or, for K == 0,
+    voltages [B][2][T][C] complex128."""
+    x = np.ascontiguousarray(x)
+    S, C, T = x.shape[:3]
+    pos, dirs, freq = _f64(pos), _f64(dirs), _f64(freq)
+    B = dirs.shape[0]
+    refp = None if ref is None else _f64(ref)
+    if K == 0:
+        out = np.empty((B, 2, T, C, 2))
+    else:
+        out = np.empty((B, K, T // t_int, C // f_int))
+    rc = _load().lbfo_pipeline(x.ctypes.data, _xtype_of(x), S, C, T, pos, dirs, B,
+                               None if refp is None else refp.ctypes.data, freq, K, t_int, f_int,
+                               nthreads, out)
+    if rc != 0:
+        raise ValueError("oracle pipeline rejected its arguments")
+    if K == 0:
+        return out[..., 0] + 1j * out[..., 1]
+    return out
+
+
+def block_weights(blk, use_ref: bool = True) -> np.ndarray:
+    """Weights of a synthetic block (complex128 [C][B][S])."""
+    return weights(delays(blk.station_xyz, blk.beam_dir, blk.ref_dir if use_ref else None), blk.freq_hz)
