@@ -1,0 +1,230 @@
+/*
+ * lbf.h -- C ABI of an MI355X-native tied-array beam former.
+ *
+ * The operations follow Mol & Romein, "The LOFAR Beam Former: Implementation
+ * and Performance Analysis" (arxiv 1105.0661).  Section numbers below refer to
+ * that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named d_* are DEVICE pointers owned by the caller.  The library
+ *    never frees them and never keeps them after the work queued on `stream`
+ *    has completed.  Other pointers are host pointers, read before the call
+ *    returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every compute call is asynchronous on that stream: results are ready
+ *    once the caller synchronises the stream.
+ *  - Every call returns an lbf_status.  On a non-zero status nothing has been
+ *    queued and no output has been written; lbf_last_error() returns a text for
+ *    the calling thread.  No call aborts, throws or prints.
+ *  - Complex values are stored as interleaved (re, im) pairs.
+ *  - Symbols: S stations, B tied-array beams, C channels, T time samples per
+ *    channel, 2 polarisations (X, Y), K Stokes parameters (1: I, 4: IQUV),
+ *    t_int / f_int integration factors, T' = T / t_int, C' = C / f_int.
+ */
+#ifndef LBF_H
+#define LBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBF_OK = 0,
+    LBF_E_INVAL = -1,        /* malformed argument (size, NULL, divisibility)     */
+    LBF_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. type combination) */
+    LBF_E_NOMEM = -3,        /* does not fit the memory the caller provided       */
+    LBF_E_HIP = -4,          /* the HIP runtime reported an error                 */
+    LBF_E_BUSY = -5,         /* a bounded queue is full; retry later              */
+    LBF_E_NOTFOUND = -6      /* unknown ticket / handle                           */
+} lbf_status;
+
+/* station sample type (Section 3: dual-polarisation complex 16-bit samples;
+ * 8-bit station mode and complex float32 are also accepted) */
+typedef enum { LBF_CI8 = 0, LBF_CI16 = 1, LBF_CF32 = 2 } lbf_input_t;
+
+/* operand type of the weighted sum; accumulation is always FP32 */
+typedef enum { LBF_F32 = 0, LBF_F16 = 1, LBF_BF16 = 2 } lbf_compute_t;
+
+/* data product (Section 3: complex voltages, Stokes IQUV, Stokes I) */
+typedef enum { LBF_VOLTAGES = 0, LBF_STOKES_I = 1, LBF_STOKES_IQUV = 4 } lbf_product_t;
+
+/* Thread-local text describing the last non-zero status of this thread. */
+const char* lbf_last_error(void);
+
+/* Library version string, e.g. "lbf 1.0 gfx950". */
+const char* lbf_version(void);
+
+/*
+ * Geometric delays and complex weights (Section 3; Section 4.3: each beam's
+ * weights depend on the station location, the channel frequency and the beam
+ * coordinates).
+ *
+ *   tau[b][s] = p_s . (u_b - u_ref) / c0           (u_ref = 0 if ref_dir NULL)
+ *   w[c][b][s] = exp(-2 pi i (m - rint(m))),  m = f_c * tau[b][s]
+ *
+ * Computed in FP64 on the device, then rounded once (round-to-nearest-even)
+ * to the weight type.
+ *   d_station_xyz [S][3] f64, metres (local East-North-Up frame)
+ *   d_beam_dir    [B][3] f64, unit direction vectors
+ *   ref_dir       HOST [3] f64 or NULL
+ *   d_freq_hz     [C]    f64
+ *   d_w           [C][B][S] complex of wtype (complex f32: 8 bytes; complex
+ *                 f16 / bf16: 4 bytes per weight)
+ *   d_tau         [B][S] f64 seconds, or NULL
+ * Errors: LBF_E_INVAL for sizes < 1, NULL d_* inputs/outputs, unknown wtype.
+ */
+int lbf_compute_weights(const double* d_station_xyz, int S, const double* d_beam_dir, int B,
+                        const double* ref_dir, const double* d_freq_hz, int C, int wtype,
+                        void* d_w, double* d_tau, void* stream);
+
+/*
+ * One beam-forming block (Section 4.3): per channel, the weighted complex
+ * sum of all station signals into every tied-array beam,
+ *   y[c][b][t][p] = sum_s w[c][b][s] x[s][c][t][p],
+ * followed for the Stokes products by Stokes detection (Section 4.5),
+ * integration over t_int samples and f_int adjacent channels (Section 5.1)
+ * and the per-beam, per-Stokes final order (Section 4.6).
+ */
+typedef struct {
+    const void* d_x;   /* [S][C][T][2] complex of xtype                              */
+    int xtype;         /* lbf_input_t                                                */
+    int S, C, T;
+    const void* d_w;   /* [C][B][S] complex of ctype (from lbf_compute_weights)      */
+    int ctype;         /* lbf_compute_t: operand type of the contraction             */
+    int B;
+    int product;       /* lbf_product_t                                              */
+    int t_int, f_int;  /* Stokes only: T % t_int == 0, C % f_int == 0; voltages: 1,1 */
+    void* d_out;       /* VOLTAGES: complex f32 [C][B][T][2];
+                          STOKES:   f32 [B][K][T'][C'] (beam-major final order)       */
+} lbf_block;
+
+/*
+ * Run one block.  The Stokes products are fused: detection, integration and
+ * the beam-major store happen in the epilogue of the contraction kernel.
+ * Errors: LBF_E_INVAL (sizes < 1, NULL pointers, T % t_int, C % f_int,
+ * t_int/f_int != 1 for voltages, unknown enums); LBF_E_UNSUPPORTED for a Stokes
+ * block whose t_int is not a power of two (use lbf_beamform with VOLTAGES,
+ * then lbf_stokes, which accepts any divisor).
+ */
+int lbf_beamform(const lbf_block* blk, void* stream);
+
+/*
+ * Several independent blocks (Section 7: independent observations processed
+ * in parallel) in ONE launch of a persistent kernel that pulls
+ * (block, channel-group) work items from a device queue.  Each block's result
+ * is bitwise identical to lbf_beamform on that block alone.  All blocks must
+ * be Stokes products with ctype F16 or BF16.  n <= LBF_MAX_BATCH.
+ * Errors: as lbf_beamform, per block; LBF_E_INVAL if n < 1 or n > LBF_MAX_BATCH.
+ */
+#define LBF_MAX_BATCH 32
+int lbf_beamform_batch(const lbf_block* blks, int n, void* stream);
+
+/*
+ * Stokes detection + integration of complex voltages (the unfused path,
+ * Section 4.5):  I = |X|^2 + |Y|^2, Q = |X|^2 - |Y|^2, U = 2 Re(X conj Y),
+ * V = 2 Im(X conj Y), summed over t_int samples and f_int channels.
+ *   d_y  complex f32 [C][B][T][2]
+ *   d_s  f32 [C'][B][T'][K]    (K = product: 1 or 4)
+ * Any t_int dividing T and f_int dividing C is accepted.
+ */
+int lbf_stokes(const float* d_y, int B, int C, int T, int product, int t_int, int f_int,
+               float* d_s, void* stream);
+
+/*
+ * Reorder into the final per-beam order (Section 4.6):
+ *   out[b][k][t][c] = in[c][b][t][k]
+ * for elements of elem_bytes = 4 (f32 Stokes) or 8 (complex f32 voltages,
+ * with K = 2 polarisations).  in and out must not overlap.
+ */
+int lbf_transpose(const void* d_in, int C2, int B, int T2, int K, int elem_bytes, void* d_out,
+                  void* stream);
+
+/*
+ * Incoherent beam (Section 3): unweighted accumulation of the station powers,
+ *   inc[k][t'][c'] = sum over the t_int x f_int group of sum_s Stokes_k(x_s),
+ * laid out like one beam of the Stokes product.
+ *   d_x [S][C][T][2] complex of xtype;  d_out f32 [K][T'][C']
+ */
+int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product, int t_int,
+                   int f_int, float* d_out, void* stream);
+
+/* Bytes of each operand of a block (host arithmetic, no device access). */
+typedef struct {
+    uint64_t input_bytes, weight_bytes, output_bytes;
+    double flops;          /* 8 flops per complex multiply-add, both polarisations */
+} lbf_block_sizes;
+int lbf_block_footprint(const lbf_block* blk, lbf_block_sizes* out);
+
+/* ------------------------------------------------------------------------ */
+/* Streaming server (Section 4.1: the station stream is cut into blocks;
+ * Section 7: independent observations run in parallel as long as resources
+ * allow).  Jobs are queued on the host, admitted when their device footprint
+ * fits the caller's arena and an in-flight slot is free, and run on a pool of
+ * HIP streams; several admitted jobs are fused into one persistent launch.
+ * Weights are cached on the device per observation id.                     */
+
+typedef struct lbf_server lbf_server;
+
+typedef struct {
+    void* d_arena;            /* caller-owned device memory the server sub-allocates */
+    uint64_t arena_bytes;
+    int max_inflight;         /* jobs on the device at once (>= 1)                  */
+    int n_streams;            /* HIP streams in the pool (>= 1, default priority)   */
+    int queue_capacity;       /* host queue bound (>= 1); submit returns BUSY beyond */
+    int max_batch;            /* jobs fused per launch (1..LBF_MAX_BATCH)            */
+    int device;               /* HIP device ordinal                                  */
+} lbf_server_cfg;
+
+typedef struct {
+    uint64_t obs_id;          /* weight-cache key: same geometry and frequencies     */
+    const double* station_xyz; int S;   /* HOST [S][3] f64, copied at submit         */
+    const double* beam_dir; int B;      /* HOST [B][3] f64, copied at submit         */
+    const double* ref_dir;              /* HOST [3] f64 or NULL                      */
+    const double* freq_hz; int C;       /* HOST [C] f64, copied at submit            */
+    const void* x; int xtype; int T;    /* station samples [S][C][T][2]              */
+    int x_on_host;            /* 1: x is HOST memory, copied into the arena;
+                                 0: x is device memory valid until the job is DONE  */
+    int ctype, product, t_int, f_int;
+    void* d_out;              /* caller-owned device output, layout as lbf_beamform  */
+} lbf_job;
+
+typedef enum { LBF_JOB_QUEUED = 0, LBF_JOB_ADMITTED = 1, LBF_JOB_RUNNING = 2, LBF_JOB_DONE = 3,
+               LBF_JOB_FAILED = 4 } lbf_job_state;
+
+typedef struct {
+    int state;                /* lbf_job_state                                         */
+    int error;                /* lbf_status of a FAILED job                            */
+    uint64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns;  /* steady clock, ns       */
+    int batch_size;           /* jobs in the launch that ran this job                  */
+} lbf_job_status;
+
+/* Errors: LBF_E_INVAL for a malformed cfg; LBF_E_HIP if the device or streams
+ * cannot be set up. */
+int lbf_server_create(const lbf_server_cfg* cfg, lbf_server** out);
+
+/* Non-blocking.  LBF_E_INVAL for a malformed job, LBF_E_NOMEM if its footprint
+ * can never fit the arena, LBF_E_BUSY if the host queue is full. */
+int lbf_server_submit(lbf_server* srv, const lbf_job* job, uint64_t* ticket);
+
+/* LBF_E_NOTFOUND for an unknown ticket.  A DONE/FAILED ticket stays
+ * queryable until lbf_server_release. */
+int lbf_server_poll(lbf_server* srv, uint64_t ticket, lbf_job_status* st);
+
+/* Block until the ticket is DONE or FAILED (or timeout_ms elapses: LBF_E_BUSY). */
+int lbf_server_wait(lbf_server* srv, uint64_t ticket, int timeout_ms, lbf_job_status* st);
+
+/* Forget a finished ticket. */
+int lbf_server_release(lbf_server* srv, uint64_t ticket);
+
+/* Drain all queued and running jobs, then free the server's own state (never
+ * the caller's arena or outputs). */
+int lbf_server_destroy(lbf_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBF_H */

@@ -1,0 +1,225 @@
+// abi.cpp -- the extern "C" entry points of liblbf: argument validation,
+// error reporting and dispatch to the kernel launchers.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/lbf.h"
+#include "lbf_launch.h"
+
+static_assert(LBF_MAX_BATCH == lbf::kMaxBatch, "batch bound mismatch");
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(LBF_E_HIP, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+int ok() {
+    return LBF_OK;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int bytes_per_complex(int xtype) { return xtype == LBF_CI8 ? 2 : xtype == LBF_CI16 ? 4 : 8; }
+int weight_bytes(int ctype) { return ctype == LBF_F32 ? 8 : 4; }
+
+// Validate a block; `where` names the entry point in the error text.
+int check_block(const lbf_block* b, const char* where) {
+    if (!b) return fail(LBF_E_INVAL, "%s: block is NULL", where);
+    if (b->S < 1 || b->C < 1 || b->T < 1 || b->B < 1)
+        return fail(LBF_E_INVAL, "%s: sizes must be >= 1 (S=%d C=%d T=%d B=%d)", where, b->S, b->C, b->T, b->B);
+    if (!b->d_x || !b->d_w || !b->d_out) return fail(LBF_E_INVAL, "%s: NULL device pointer", where);
+    if (b->xtype < LBF_CI8 || b->xtype > LBF_CF32) return fail(LBF_E_INVAL, "%s: unknown xtype %d", where, b->xtype);
+    if (b->ctype < LBF_F32 || b->ctype > LBF_BF16) return fail(LBF_E_INVAL, "%s: unknown ctype %d", where, b->ctype);
+    if (b->product != LBF_VOLTAGES && b->product != LBF_STOKES_I && b->product != LBF_STOKES_IQUV)
+        return fail(LBF_E_INVAL, "%s: unknown product %d", where, b->product);
+    if (b->t_int < 1 || b->f_int < 1)
+        return fail(LBF_E_INVAL, "%s: t_int and f_int must be >= 1 (%d, %d)", where, b->t_int, b->f_int);
+    if (b->product == LBF_VOLTAGES) {
+        if (b->t_int != 1 || b->f_int != 1)
+            return fail(LBF_E_INVAL, "%s: voltages take t_int = f_int = 1", where);
+    } else {
+        if (b->T % b->t_int) return fail(LBF_E_INVAL, "%s: T=%d not a multiple of t_int=%d", where, b->T, b->t_int);
+        if (b->C % b->f_int) return fail(LBF_E_INVAL, "%s: C=%d not a multiple of f_int=%d", where, b->C, b->f_int);
+        if (!is_pow2(b->t_int))
+            return fail(LBF_E_UNSUPPORTED, "%s: fused Stokes needs a power-of-two t_int (got %d); "
+                        "use VOLTAGES + lbf_stokes", where, b->t_int);
+    }
+    if ((long long)b->C * b->T > (1LL << 40) || (long long)b->B * b->S > (1LL << 31))
+        return fail(LBF_E_INVAL, "%s: block too large", where);
+    return LBF_OK;
+}
+
+lbf::BlockDesc to_desc(const lbf_block* b) {
+    lbf::BlockDesc d;
+    d.x = b->d_x;
+    d.w = b->d_w;
+    d.out = b->d_out;
+    d.S = b->S; d.C = b->C; d.T = b->T; d.B = b->B;
+    d.xtype = b->xtype; d.ctype = b->ctype; d.product = b->product;
+    d.t_int = b->product == LBF_VOLTAGES ? 1 : b->t_int;
+    d.f_int = b->product == LBF_VOLTAGES ? 1 : b->f_int;
+    return d;
+}
+
+// Work counters of the persistent batch kernel: a ring of slots per device so
+// that batches queued on different streams do not share a counter.
+constexpr int kCounterSlots = 1024;
+std::mutex g_counter_mu;
+int* g_counters[64] = {nullptr};
+unsigned g_counter_next[64] = {0};
+
+int counter_slot(int** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "lbf_beamform_batch");
+    if (dev < 0 || dev >= 64) return fail(LBF_E_UNSUPPORTED, "lbf_beamform_batch: device %d", dev);
+    std::lock_guard<std::mutex> lk(g_counter_mu);
+    if (!g_counters[dev]) {
+        e = hipMalloc((void**)&g_counters[dev], sizeof(int) * kCounterSlots);
+        if (e != hipSuccess) return hip_fail(e, "lbf_beamform_batch: counter allocation");
+    }
+    *out = g_counters[dev] + (g_counter_next[dev]++ % kCounterSlots);
+    return LBF_OK;
+}
+
+}  // namespace
+
+int lbf::set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+extern "C" {
+
+const char* lbf_last_error(void) { return g_err.c_str(); }
+
+const char* lbf_version(void) { return "lbf 1.0 gfx950"; }
+
+int lbf_compute_weights(const double* d_station_xyz, int S, const double* d_beam_dir, int B, const double* ref_dir,
+                        const double* d_freq_hz, int C, int wtype, void* d_w, double* d_tau, void* stream) {
+    if (S < 1 || B < 1 || C < 1)
+        return fail(LBF_E_INVAL, "lbf_compute_weights: sizes must be >= 1 (S=%d B=%d C=%d)", S, B, C);
+    if (!d_station_xyz || !d_beam_dir || !d_freq_hz || !d_w)
+        return fail(LBF_E_INVAL, "lbf_compute_weights: NULL device pointer");
+    if (wtype < LBF_F32 || wtype > LBF_BF16) return fail(LBF_E_INVAL, "lbf_compute_weights: unknown wtype %d", wtype);
+    const double rx = ref_dir ? ref_dir[0] : 0.0, ry = ref_dir ? ref_dir[1] : 0.0, rz = ref_dir ? ref_dir[2] : 0.0;
+    hipError_t e = lbf::launch_weights(d_station_xyz, S, d_beam_dir, B, rx, ry, rz, d_freq_hz, C, wtype, d_w, d_tau,
+                                       (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_compute_weights");
+    return ok();
+}
+
+int lbf_beamform(const lbf_block* blk, void* stream) {
+    int rc = check_block(blk, "lbf_beamform");
+    if (rc) return rc;
+    hipError_t e = lbf::launch_beamform(to_desc(blk), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_beamform");
+    return ok();
+}
+
+int lbf_beamform_batch(const lbf_block* blks, int n, void* stream) {
+    if (!blks) return fail(LBF_E_INVAL, "lbf_beamform_batch: blocks is NULL");
+    if (n < 1 || n > LBF_MAX_BATCH) return fail(LBF_E_INVAL, "lbf_beamform_batch: n=%d outside 1..%d", n, LBF_MAX_BATCH);
+    lbf::BlockDesc d[lbf::kMaxBatch];
+    for (int i = 0; i < n; ++i) {
+        int rc = check_block(&blks[i], "lbf_beamform_batch");
+        if (rc) return rc;
+        if (blks[i].product == LBF_VOLTAGES)
+            return fail(LBF_E_UNSUPPORTED, "lbf_beamform_batch: block %d: batches take Stokes products", i);
+        if (blks[i].ctype == LBF_F32)
+            return fail(LBF_E_UNSUPPORTED, "lbf_beamform_batch: block %d: batches take F16 or BF16 operands", i);
+        if (blks[i].ctype != blks[0].ctype)
+            return fail(LBF_E_UNSUPPORTED, "lbf_beamform_batch: all blocks of a batch share one ctype");
+        d[i] = to_desc(&blks[i]);
+    }
+    int* counter = nullptr;
+    int rc = counter_slot(&counter);
+    if (rc) return rc;
+    hipError_t e = lbf::launch_beamform_batch(d, n, counter, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_beamform_batch");
+    return ok();
+}
+
+int lbf_stokes(const float* d_y, int B, int C, int T, int product, int t_int, int f_int, float* d_s, void* stream) {
+    if (B < 1 || C < 1 || T < 1) return fail(LBF_E_INVAL, "lbf_stokes: sizes must be >= 1");
+    if (!d_y || !d_s) return fail(LBF_E_INVAL, "lbf_stokes: NULL device pointer");
+    if (product != LBF_STOKES_I && product != LBF_STOKES_IQUV)
+        return fail(LBF_E_INVAL, "lbf_stokes: product must be STOKES_I or STOKES_IQUV (got %d)", product);
+    if (t_int < 1 || f_int < 1 || T % t_int || C % f_int)
+        return fail(LBF_E_INVAL, "lbf_stokes: t_int=%d must divide T=%d and f_int=%d must divide C=%d", t_int, T,
+                    f_int, C);
+    hipError_t e = lbf::launch_stokes(d_y, B, C, T, product, t_int, f_int, d_s, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_stokes");
+    return ok();
+}
+
+int lbf_transpose(const void* d_in, int C2, int B, int T2, int K, int elem_bytes, void* d_out, void* stream) {
+    if (C2 < 1 || B < 1 || T2 < 1 || K < 1) return fail(LBF_E_INVAL, "lbf_transpose: sizes must be >= 1");
+    if (!d_in || !d_out) return fail(LBF_E_INVAL, "lbf_transpose: NULL device pointer");
+    if (elem_bytes != 4 && elem_bytes != 8) return fail(LBF_E_INVAL, "lbf_transpose: elem_bytes must be 4 or 8");
+    const size_t bytes = (size_t)C2 * B * T2 * K * elem_bytes;
+    const char* a = (const char*)d_in;
+    const char* b = (const char*)d_out;
+    if (a < b + bytes && b < a + bytes) return fail(LBF_E_INVAL, "lbf_transpose: input and output overlap");
+    if ((long long)B * T2 * K > (1LL << 40) / 32) return fail(LBF_E_INVAL, "lbf_transpose: too large");
+    hipError_t e = lbf::launch_transpose(d_in, C2, B, T2, K, elem_bytes, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_transpose");
+    return ok();
+}
+
+int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product, int t_int, int f_int, float* d_out,
+                   void* stream) {
+    if (S < 1 || C < 1 || T < 1) return fail(LBF_E_INVAL, "lbf_incoherent: sizes must be >= 1");
+    if (!d_x || !d_out) return fail(LBF_E_INVAL, "lbf_incoherent: NULL device pointer");
+    if (xtype < LBF_CI8 || xtype > LBF_CF32) return fail(LBF_E_INVAL, "lbf_incoherent: unknown xtype %d", xtype);
+    if (product != LBF_STOKES_I && product != LBF_STOKES_IQUV)
+        return fail(LBF_E_INVAL, "lbf_incoherent: product must be STOKES_I or STOKES_IQUV");
+    if (t_int < 1 || f_int < 1 || T % t_int || C % f_int)
+        return fail(LBF_E_INVAL, "lbf_incoherent: t_int must divide T and f_int must divide C");
+    hipError_t e = lbf::launch_incoherent(d_x, xtype, S, C, T, product, t_int, f_int, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_incoherent");
+    return ok();
+}
+
+int lbf_block_footprint(const lbf_block* b, lbf_block_sizes* out) {
+    if (!out) return fail(LBF_E_INVAL, "lbf_block_footprint: out is NULL");
+    if (!b) return fail(LBF_E_INVAL, "lbf_block_footprint: block is NULL");
+    if (b->S < 1 || b->C < 1 || b->T < 1 || b->B < 1 || b->t_int < 1 || b->f_int < 1)
+        return fail(LBF_E_INVAL, "lbf_block_footprint: sizes must be >= 1");
+    if (b->xtype < LBF_CI8 || b->xtype > LBF_CF32 || b->ctype < LBF_F32 || b->ctype > LBF_BF16)
+        return fail(LBF_E_INVAL, "lbf_block_footprint: unknown type");
+    if (b->product != LBF_VOLTAGES && b->product != LBF_STOKES_I && b->product != LBF_STOKES_IQUV)
+        return fail(LBF_E_INVAL, "lbf_block_footprint: unknown product");
+    const uint64_t S = b->S, C = b->C, T = b->T, B = b->B;
+    out->input_bytes = S * C * T * 2 * bytes_per_complex(b->xtype);
+    out->weight_bytes = C * B * S * weight_bytes(b->ctype);
+    if (b->product == LBF_VOLTAGES) out->output_bytes = C * B * T * 2 * 8;
+    else out->output_bytes = B * (uint64_t)b->product * (T / b->t_int) * (C / b->f_int) * 4;
+    out->flops = 8.0 * (double)B * (double)S * (double)C * (double)T * 2.0;
+    return ok();
+}
+
+}  // extern "C"

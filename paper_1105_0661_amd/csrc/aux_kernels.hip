@@ -1,0 +1,210 @@
+// aux_kernels.hip -- weights (FP64), unfused Stokes, final-order transpose and
+// the incoherent beam.
+#include "lbf_device.h"
+#include "lbf_launch.h"
+
+namespace lbf {
+
+// ---------------------------------------------------------------------------
+// Weights (Section 3 and Section 4.3 of Mol & Romein): the delay of station s
+// for beam b, tau = p_s . (u_b - u_ref) / c0, and the phase-shift weight
+// w = exp(-2 pi i frac(f tau)).  Everything up to the final rounding is FP64:
+// f * tau spans many turns and only its fractional part matters.
+// One thread per (c, b, s), s fastest, so stores are coalesced.
+// ---------------------------------------------------------------------------
+constexpr double kC0 = 299792458.0;
+
+template <int WT>
+__global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__ pos, int S,
+                                                      const double* __restrict__ dir, int B, double rx, double ry,
+                                                      double rz, const double* __restrict__ freq, int C, void* w,
+                                                      double* tau) {
+    const size_t n = (size_t)C * B * S;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int s = (int)(i % S);
+        const size_t cb = i / S;
+        const int b = (int)(cb % B);
+        const int c = (int)(cb / B);
+        const double dx = dir[3 * b + 0] - rx, dy = dir[3 * b + 1] - ry, dz = dir[3 * b + 2] - rz;
+        const double proj = pos[3 * s + 0] * dx + pos[3 * s + 1] * dy + pos[3 * s + 2] * dz;
+        const double t = proj / kC0;
+        if (tau != nullptr && c == 0) tau[(size_t)b * S + s] = t;
+        const double m = freq[c] * t;
+        const double r = m - rint(m);          // fractional turn in [-0.5, 0.5]
+        double sn, cs;
+        sincospi(2.0 * r, &sn, &cs);
+        const double wr = cs, wi = -sn;
+        if (WT == CT_F32) {
+            float2 v;
+            v.x = (float)wr;
+            v.y = (float)wi;
+            reinterpret_cast<float2*>(w)[i] = v;
+        } else if (WT == CT_F16) {
+            reinterpret_cast<uint32_t*>(w)[i] = pack16(f64_to_f16_bits(wr), f64_to_f16_bits(wi));
+        } else {
+            reinterpret_cast<uint32_t*>(w)[i] = pack16(f64_to_bf16_bits(wr), f64_to_bf16_bits(wi));
+        }
+    }
+}
+
+hipError_t launch_weights(const double* pos, int S, const double* dir, int B, double rx, double ry, double rz,
+                          const double* freq, int C, int wtype, void* w, double* tau, hipStream_t st) {
+    const size_t n = (size_t)C * B * S;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    dim3 g((unsigned)blocks), b(256);
+    if (wtype == CT_F32) hipLaunchKernelGGL(weights_kernel<CT_F32>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, freq, C, w, tau);
+    else if (wtype == CT_F16) hipLaunchKernelGGL(weights_kernel<CT_F16>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, freq, C, w, tau);
+    else hipLaunchKernelGGL(weights_kernel<CT_BF16>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, freq, C, w, tau);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Unfused Stokes detection + integration (Section 4.5; Section 5.1):
+// y [C][B][T][2] complex f32 -> s [C'][B][T'][K].  One thread per output
+// (c', b, t'); any t_int | T and f_int | C.  Sum order: channel, then time.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(256) void stokes_kernel(const floatx4* __restrict__ y, int B, int C, int T, int t_int,
+                                                     int f_int, float* __restrict__ s) {
+    const int T2 = T / t_int, C2 = C / f_int;
+    const size_t n = (size_t)C2 * B * T2;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int t2 = (int)(i % T2);
+        const size_t cb = i / T2;
+        const int b = (int)(cb % B);
+        const int c2 = (int)(cb / B);
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int dc = 0; dc < f_int; ++dc) {
+            const int c = c2 * f_int + dc;
+            const floatx4* row = y + ((size_t)c * B + b) * T + (size_t)t2 * t_int;
+            for (int dt = 0; dt < t_int; ++dt) {
+                const floatx4 v = row[dt];
+                const float xx = v[0] * v[0] + v[1] * v[1];
+                const float yy = v[2] * v[2] + v[3] * v[3];
+                acc[0] += xx + yy;
+                if (K == 4) {
+                    acc[1] += xx - yy;
+                    acc[2] += 2.0f * (v[0] * v[2] + v[1] * v[3]);
+                    acc[3] += 2.0f * (v[1] * v[2] - v[0] * v[3]);
+                }
+            }
+        }
+        if (K == 4) {
+            floatx4 o;
+            o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3];
+            reinterpret_cast<floatx4*>(s)[i] = o;
+        } else {
+            s[i] = acc[0];
+        }
+    }
+}
+
+hipError_t launch_stokes(const float* y, int B, int C, int T, int product, int t_int, int f_int, float* s,
+                         hipStream_t st) {
+    const size_t n = (size_t)(C / f_int) * B * (T / t_int);
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks == 0) blocks = 1;
+    const floatx4* yy = reinterpret_cast<const floatx4*>(y);
+    if (product == PR_IQUV)
+        hipLaunchKernelGGL(stokes_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, yy, B, C, T, t_int, f_int, s);
+    else
+        hipLaunchKernelGGL(stokes_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, yy, B, C, T, t_int, f_int, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Final order (Section 4.6): out[b][k][t][c] = in[c][b][t][k].  Viewing the
+// input as a C2 x M matrix (M = B*T2*K), 32x32 tiles go through LDS so both
+// the reads (along m) and the writes (along c) are coalesced.
+// ---------------------------------------------------------------------------
+template <typename E>
+__global__ __launch_bounds__(256) void transpose_kernel(const E* __restrict__ in, int C2, int B, int T2, int K,
+                                                        E* __restrict__ out) {
+    __shared__ E tile[32][33];
+    const long M = (long)B * T2 * K;
+    const long m0 = (long)blockIdx.x * 32;
+    const int c0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int c = c0 + r;
+        const long m = m0 + tx;
+        if (c < C2 && m < M) tile[r][tx] = in[(size_t)c * M + m];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const long m = m0 + r;
+        const int c = c0 + tx;
+        if (c < C2 && m < M) {
+            const int k = (int)(m % K);
+            const long bt = m / K;
+            const int t = (int)(bt % T2);
+            const int b = (int)(bt / T2);
+            out[(((size_t)b * K + k) * T2 + t) * C2 + c] = tile[tx][r];
+        }
+    }
+}
+
+hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int elem_bytes, void* out,
+                            hipStream_t st) {
+    const long M = (long)B * T2 * K;
+    dim3 g((unsigned)((M + 31) / 32), (unsigned)((C2 + 31) / 32)), b(256);
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(transpose_kernel<float>, g, b, 0, st, (const float*)in, C2, B, T2, K, (float*)out);
+    else
+        hipLaunchKernelGGL(transpose_kernel<float2>, g, b, 0, st, (const float2*)in, C2, B, T2, K, (float2*)out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Incoherent beam (Section 3): sum over stations of each station's Stokes
+// parameters, integrated like a tied-array beam.  One thread per output
+// (c', t'); loops channel, time, station; reads are along t for a station.
+// out [K][T'][C'].
+// ---------------------------------------------------------------------------
+template <int XT, int K>
+__global__ __launch_bounds__(256) void incoherent_kernel(const void* __restrict__ x, int S, int C, int T, int t_int,
+                                                         int f_int, float* __restrict__ out) {
+    const int T2 = T / t_int, C2 = C / f_int;
+    const size_t n = (size_t)C2 * T2;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(i % C2);
+        const int t2 = (int)(i / C2);
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int dc = 0; dc < f_int; ++dc)
+            for (int dt = 0; dt < t_int; ++dt)
+                for (int s = 0; s < S; ++s) {
+                    const int c = c2 * f_int + dc, t = t2 * t_int + dt;
+                    const floatx4 v = Sample<XT>::load(x, ((size_t)s * C + c) * T + t);
+                    const float xx = v[0] * v[0] + v[1] * v[1];
+                    const float yy = v[2] * v[2] + v[3] * v[3];
+                    acc[0] += xx + yy;
+                    if (K == 4) {
+                        acc[1] += xx - yy;
+                        acc[2] += 2.0f * (v[0] * v[2] + v[1] * v[3]);
+                        acc[3] += 2.0f * (v[1] * v[2] - v[0] * v[3]);
+                    }
+                }
+        for (int k = 0; k < K; ++k) out[((size_t)k * T2 + t2) * C2 + c2] = acc[k];
+    }
+}
+
+hipError_t launch_incoherent(const void* x, int xtype, int S, int C, int T, int product, int t_int, int f_int,
+                             float* out, hipStream_t st) {
+    const size_t n = (size_t)(C / f_int) * (T / t_int);
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks == 0) blocks = 1;
+    dim3 g((unsigned)blocks), b(256);
+#define LBF_INC(XTV)                                                                                        \
+    if (product == PR_IQUV) hipLaunchKernelGGL((incoherent_kernel<XTV, 4>), g, b, 0, st, x, S, C, T, t_int, f_int, out); \
+    else hipLaunchKernelGGL((incoherent_kernel<XTV, 1>), g, b, 0, st, x, S, C, T, t_int, f_int, out);
+    if (xtype == XT_CI8) { LBF_INC(XT_CI8) }
+    else if (xtype == XT_CI16) { LBF_INC(XT_CI16) }
+    else { LBF_INC(XT_CF32) }
+#undef LBF_INC
+    return hipGetLastError();
+}
+
+}  // namespace lbf

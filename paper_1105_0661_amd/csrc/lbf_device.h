@@ -1,0 +1,137 @@
+// lbf_device.h -- device-side types and helpers shared by the lbf kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbf {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef char charx4 __attribute__((ext_vector_type(4)));
+
+enum { XT_CI8 = 0, XT_CI16 = 1, XT_CF32 = 2 };
+enum { CT_F32 = 0, CT_F16 = 1, CT_BF16 = 2 };
+enum { PR_VOLT = 0, PR_I = 1, PR_IQUV = 4 };
+
+constexpr int kWave = 64;
+constexpr int kTile = 32;            // MFMA 32x32 output tile: 32 samples x 32 beams
+constexpr int kXcds = 8;             // MI355X: 8 XCDs, blocks dispatched round-robin
+constexpr int kCusPerXcd = 32;
+
+// One beam-forming block as the kernels see it (mirrors lbf_block).
+struct BlockDesc {
+    const void* x;      // [S][C][T][2] complex
+    const void* w;      // [C][B][S] complex
+    void* out;          // voltages [C][B][T][2] cf32, or Stokes [B][K][T'][C'] f32
+    int S, C, T, B;
+    int xtype, ctype, product;
+    int t_int, f_int;
+};
+
+// ---------------------------------------------------------------------------
+// sample loads: one time sample of one station, both polarisations
+// (Xre, Xim, Yre, Yim) as floats.  Indices are checked by the caller.
+// ---------------------------------------------------------------------------
+template <int XT> struct Sample;
+
+template <> struct Sample<XT_CI8> {
+    static constexpr int bytes = 4;
+    __device__ static inline floatx4 load(const void* base, size_t idx) {
+        const int v = __builtin_nontemporal_load(reinterpret_cast<const int*>(base) + idx);
+        floatx4 r;
+        r[0] = (float)(int8_t)(v & 0xff);
+        r[1] = (float)(int8_t)((v >> 8) & 0xff);
+        r[2] = (float)(int8_t)((v >> 16) & 0xff);
+        r[3] = (float)(int8_t)((v >> 24) & 0xff);
+        return r;
+    }
+};
+
+template <> struct Sample<XT_CI16> {
+    static constexpr int bytes = 8;
+    __device__ static inline floatx4 load(const void* base, size_t idx) {
+        const shortx4 v = reinterpret_cast<const shortx4*>(base)[idx];
+        floatx4 r;
+        r[0] = (float)v[0];
+        r[1] = (float)v[1];
+        r[2] = (float)v[2];
+        r[3] = (float)v[3];
+        return r;
+    }
+};
+
+template <> struct Sample<XT_CF32> {
+    static constexpr int bytes = 16;
+    __device__ static inline floatx4 load(const void* base, size_t idx) {
+        return reinterpret_cast<const floatx4*>(base)[idx];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// FP64 -> narrow conversions with a single round-to-nearest-even.
+// Going through float with round-to-odd keeps one rounding: float carries
+// 24 significand bits, at least 2 more than f16 (11) or bf16 (8).
+// ---------------------------------------------------------------------------
+__device__ inline float f64_to_f32_round_odd(double d) {
+    float f = __double2float_rz(d);
+    if ((double)f != d) f = __uint_as_float(__float_as_uint(f) | 1u);
+    return f;
+}
+
+__device__ inline uint16_t f32_to_bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ inline uint16_t f64_to_f16_bits(double d) {
+    _Float16 h = (_Float16)f64_to_f32_round_odd(d);
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+__device__ inline uint16_t f64_to_bf16_bits(double d) {
+    return f32_to_bf16_bits(f64_to_f32_round_odd(d));
+}
+
+__device__ inline uint16_t f32_to_f16_bits(float f) {
+    _Float16 h = (_Float16)f;
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+// pack two 16-bit values into one 32-bit word (lo first in memory)
+__device__ inline uint32_t pack16(uint16_t lo, uint16_t hi) {
+    return (uint32_t)lo | ((uint32_t)hi << 16);
+}
+
+template <int CT> __device__ inline uint16_t f32_to_bits(float f);
+template <> __device__ inline uint16_t f32_to_bits<CT_F16>(float f) { return f32_to_f16_bits(f); }
+template <> __device__ inline uint16_t f32_to_bits<CT_BF16>(float f) { return f32_to_bf16_bits(f); }
+
+// ---------------------------------------------------------------------------
+// Sample-to-row map inside a 32-sample MFMA tile.  The 32x32 result of a
+// 32x32xK MFMA leaves, in lane (h = lane/32, col = lane%32), accumulator
+// element e at row (e/4)*8 + h*4 + e%4.  Feeding A-row r with sample
+//   t(r) = ((r >> 2) & 1) * 16 + (r >> 3) * 4 + (r & 3)
+// gives lane half h the 16 consecutive samples 16h .. 16h+15 in element
+// order, so integrations over up to 16 samples stay inside one lane.
+// ---------------------------------------------------------------------------
+__device__ inline int tile_row_sample(int r) {
+    return ((r >> 2) & 1) * 16 + (r >> 3) * 4 + (r & 3);
+}
+
+// Block index remap so that the blocks resident at the same time on one XCD
+// (blocks are dispatched round-robin over the 8 XCDs) work on adjacent items:
+// their beam-major stores then land in the same cache lines of that XCD's L2.
+__device__ inline int xcd_remap(int i, int n) {
+    constexpr int R = kXcds * kCusPerXcd;
+    const int full = (n / R) * R;
+    if (i >= full) return i;
+    const int round = i / R, j = i % R;
+    return round * R + (j % kXcds) * kCusPerXcd + j / kXcds;
+}
+
+}  // namespace lbf

@@ -1,0 +1,24 @@
+// lbf_launch.h -- host-side launchers of the lbf kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "lbf_device.h"
+
+namespace lbf {
+
+constexpr int kMaxBatch = 32;   // equals LBF_MAX_BATCH in include/lbf.h
+
+// Set the calling thread's lbf_last_error() text; returns code.
+int set_error(int code, const char* fmt, ...);
+
+hipError_t launch_weights(const double* pos, int S, const double* dir, int B, double rx, double ry, double rz,
+                          const double* freq, int C, int wtype, void* w, double* tau, hipStream_t st);
+hipError_t launch_beamform(const BlockDesc& d, hipStream_t st);
+hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, hipStream_t st);
+hipError_t launch_stokes(const float* y, int B, int C, int T, int product, int t_int, int f_int, float* s,
+                         hipStream_t st);
+hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int elem_bytes, void* out,
+                            hipStream_t st);
+hipError_t launch_incoherent(const void* x, int xtype, int S, int C, int T, int product, int t_int, int f_int,
+                             float* out, hipStream_t st);
+
+}  // namespace lbf

@@ -1,0 +1,527 @@
+// server.cpp -- streaming block server of liblbf.
+//
+// Jobs (beam-forming blocks) are queued on the host and admitted in arrival
+// order when (a) fewer than max_inflight jobs are on the device and (b) their
+// device footprint -- the weights of a not-yet-cached observation, plus the
+// station samples when they arrive in host memory -- fits the caller's arena.
+// Jobs admitted together are fused into one persistent-kernel launch
+// (lbf_beamform_batch) on the next stream of the pool, so blocks arriving
+// while others run overlap on the device.  Weights stay cached on the device
+// per observation id and are evicted least-recently-used when the arena is
+// short.  Completion is observed through HIP events by the scheduler thread.
+// (Section 4.1: the station stream is cut into short blocks; Section 7:
+// independent observations run in parallel while resources allow; Section 4.7:
+// a bounded buffer that refuses work rather than stalling the pipeline.)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lbf.h"
+#include "lbf_launch.h"
+
+namespace {
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit sub-allocator over [0, size) of the caller's arena.
+class Arena {
+  public:
+    void reset(uint64_t size) {
+        free_.clear();
+        size_ = size;
+        if (size) free_[0] = size;
+    }
+    bool alloc(uint64_t bytes, uint64_t* off) {
+        bytes = align_up(bytes ? bytes : 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const uint64_t rest = it->second - bytes, base = it->first;
+                free_.erase(it);
+                if (rest) free_[base + bytes] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t bytes) {
+        bytes = align_up(bytes ? bytes : 1);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t used() const { return used_; }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;
+    uint64_t size_ = 0, used_ = 0;
+};
+
+int bytes_per_complex(int xt) { return xt == LBF_CI8 ? 2 : xt == LBF_CI16 ? 4 : 8; }
+int weight_bytes(int ct) { return ct == LBF_F32 ? 8 : 4; }
+
+struct WeightEntry {
+    uint64_t off = 0, bytes = 0;   // weights + geometry scratch, one allocation
+    int S = 0, B = 0, C = 0, ctype = 0;
+    int refs = 0;
+    uint64_t last_use = 0;
+    hipEvent_t ready = nullptr;
+};
+
+struct JobRec {
+    uint64_t ticket = 0;
+    lbf_job job;
+    std::vector<double> pos, dir, freq;
+    double ref[3];
+    bool has_ref = false;
+    lbf_job_status st;
+    uint64_t x_off = 0, x_bytes = 0;   // staging of host samples
+    bool staged = false;
+    uint64_t wkey = 0;
+    bool new_weights = false;
+};
+
+struct Launch {
+    std::vector<uint64_t> tickets;
+    hipEvent_t done = nullptr;
+    int stream = 0;
+};
+
+}  // namespace
+
+struct lbf_server {
+    lbf_server_cfg cfg;
+    std::vector<hipStream_t> streams;
+    int next_stream = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<JobRec>> jobs;
+    std::map<uint64_t, WeightEntry> wcache;   // key: obs_id * 4 + ctype
+    std::vector<Launch> inflight;
+    int inflight_jobs = 0;
+    Arena arena;
+    uint64_t next_ticket = 1, use_clock = 0;
+    bool stop = false;
+    std::thread worker;
+    std::string err;
+};
+
+namespace {
+
+int validate_job(const lbf_job* j) {
+    using lbf::set_error;
+    if (!j) return set_error(LBF_E_INVAL, "lbf_server_submit: job is NULL");
+    if (j->S < 1 || j->B < 1 || j->C < 1 || j->T < 1)
+        return set_error(LBF_E_INVAL, "lbf_server_submit: sizes must be >= 1");
+    if (!j->station_xyz || !j->beam_dir || !j->freq_hz || !j->x || !j->d_out)
+        return set_error(LBF_E_INVAL, "lbf_server_submit: NULL pointer in job");
+    if (j->xtype < LBF_CI8 || j->xtype > LBF_CF32) return set_error(LBF_E_INVAL, "lbf_server_submit: unknown xtype");
+    if (j->ctype < LBF_F32 || j->ctype > LBF_BF16) return set_error(LBF_E_INVAL, "lbf_server_submit: unknown ctype");
+    if (j->product != LBF_VOLTAGES && j->product != LBF_STOKES_I && j->product != LBF_STOKES_IQUV)
+        return set_error(LBF_E_INVAL, "lbf_server_submit: unknown product");
+    if (j->t_int < 1 || j->f_int < 1) return set_error(LBF_E_INVAL, "lbf_server_submit: t_int, f_int must be >= 1");
+    if (j->product == LBF_VOLTAGES) {
+        if (j->t_int != 1 || j->f_int != 1)
+            return set_error(LBF_E_INVAL, "lbf_server_submit: voltages take t_int = f_int = 1");
+    } else {
+        if (j->T % j->t_int || j->C % j->f_int)
+            return set_error(LBF_E_INVAL, "lbf_server_submit: t_int must divide T and f_int must divide C");
+        if (j->t_int & (j->t_int - 1))
+            return set_error(LBF_E_UNSUPPORTED, "lbf_server_submit: t_int must be a power of two");
+    }
+    return LBF_OK;
+}
+
+uint64_t weights_alloc_bytes(const lbf_job& j) {
+    return align_up((uint64_t)j.C * j.B * j.S * weight_bytes(j.ctype)) +
+           align_up(sizeof(double) * ((uint64_t)j.S * 3 + (uint64_t)j.B * 3 + j.C));
+}
+
+uint64_t staging_bytes(const lbf_job& j) {
+    return j.x_on_host ? (uint64_t)j.S * j.C * j.T * 2 * bytes_per_complex(j.xtype) : 0;
+}
+
+char* arena_ptr(lbf_server* s, uint64_t off) { return (char*)s->cfg.d_arena + off; }
+
+// Try to place a job's device state.  Called with the lock held.
+bool try_admit(lbf_server* s, JobRec* r) {
+    const lbf_job& j = r->job;
+    const uint64_t key = j.obs_id * 4 + (uint64_t)j.ctype;
+    auto it = s->wcache.find(key);
+    bool hit = it != s->wcache.end() && it->second.S == j.S && it->second.B == j.B && it->second.C == j.C;
+    if (it != s->wcache.end() && !hit && it->second.refs > 0) return false;   // same id, other shape, in use
+    const uint64_t need_w = hit ? 0 : weights_alloc_bytes(j);
+    const uint64_t need_x = staging_bytes(j);
+    uint64_t woff = 0, xoff = 0;
+    for (;;) {
+        bool okw = need_w == 0 || s->arena.alloc(need_w, &woff);
+        bool okx = true;
+        if (okw && need_x) {
+            okx = s->arena.alloc(need_x, &xoff);
+            if (!okx && need_w) s->arena.release(woff, need_w);
+        }
+        if (okw && okx) break;
+        // evict the least recently used idle weight set (never the one we need)
+        auto victim = s->wcache.end();
+        for (auto w = s->wcache.begin(); w != s->wcache.end(); ++w)
+            if (w->second.refs == 0 && w->first != key &&
+                (victim == s->wcache.end() || w->second.last_use < victim->second.last_use))
+                victim = w;
+        if (victim == s->wcache.end()) return false;
+        (void)hipEventDestroy(victim->second.ready);
+        s->arena.release(victim->second.off, victim->second.bytes);
+        s->wcache.erase(victim);
+    }
+    if (!hit) {
+        if (it != s->wcache.end()) {   // stale entry of another shape, idle
+            (void)hipEventDestroy(it->second.ready);
+            s->arena.release(it->second.off, it->second.bytes);
+            s->wcache.erase(it);
+        }
+        WeightEntry e;
+        e.off = woff;
+        e.bytes = need_w;
+        e.S = j.S; e.B = j.B; e.C = j.C; e.ctype = j.ctype;
+        (void)hipEventCreateWithFlags(&e.ready, hipEventDisableTiming);
+        s->wcache[key] = e;
+        r->new_weights = true;
+    }
+    WeightEntry& e = s->wcache[key];
+    e.refs++;
+    e.last_use = ++s->use_clock;
+    r->wkey = key;
+    if (need_x) {
+        r->x_off = xoff;
+        r->x_bytes = need_x;
+        r->staged = true;
+    }
+    return true;
+}
+
+void release_job(lbf_server* s, JobRec* r) {
+    if (r->staged) {
+        s->arena.release(r->x_off, r->x_bytes);
+        r->staged = false;
+    }
+    auto it = s->wcache.find(r->wkey);
+    if (it != s->wcache.end() && it->second.refs > 0) it->second.refs--;
+}
+
+lbf_block block_of(lbf_server* s, JobRec* r) {
+    const lbf_job& j = r->job;
+    const WeightEntry& e = s->wcache[r->wkey];
+    lbf_block b;
+    b.d_x = r->staged ? (const void*)arena_ptr(s, r->x_off) : j.x;
+    b.xtype = j.xtype;
+    b.S = j.S; b.C = j.C; b.T = j.T;
+    b.d_w = arena_ptr(s, e.off);
+    b.ctype = j.ctype;
+    b.B = j.B;
+    b.product = j.product;
+    b.t_int = j.t_int;
+    b.f_int = j.f_int;
+    b.d_out = j.d_out;
+    return b;
+}
+
+// Issue the work of a set of admitted jobs on one stream.  Called WITHOUT the
+// lock; the JobRec objects and cache entries it touches are pinned by refs.
+int issue(lbf_server* s, const std::vector<JobRec*>& rs, const std::vector<lbf_block>& blocks,
+          const std::vector<WeightEntry>& went, hipStream_t st) {
+    for (size_t i = 0; i < rs.size(); ++i) {
+        JobRec* r = rs[i];
+        const lbf_job& j = r->job;
+        const WeightEntry& e = went[i];
+        if (r->new_weights) {
+            char* base = arena_ptr(s, e.off);
+            double* geo = (double*)(base + align_up((uint64_t)j.C * j.B * j.S * weight_bytes(j.ctype)));
+            double* dpos = geo;
+            double* ddir = geo + (size_t)j.S * 3;
+            double* dfreq = ddir + (size_t)j.B * 3;
+            hipError_t he = hipMemcpyAsync(dpos, r->pos.data(), sizeof(double) * r->pos.size(), hipMemcpyHostToDevice, st);
+            if (he == hipSuccess)
+                he = hipMemcpyAsync(ddir, r->dir.data(), sizeof(double) * r->dir.size(), hipMemcpyHostToDevice, st);
+            if (he == hipSuccess)
+                he = hipMemcpyAsync(dfreq, r->freq.data(), sizeof(double) * r->freq.size(), hipMemcpyHostToDevice, st);
+            if (he != hipSuccess) return LBF_E_HIP;
+            int rc = lbf_compute_weights(dpos, j.S, ddir, j.B, r->has_ref ? r->ref : nullptr, dfreq, j.C, j.ctype, base,
+                                         nullptr, st);
+            if (rc) return rc;
+            if (hipEventRecord(e.ready, st) != hipSuccess) return LBF_E_HIP;
+        } else {
+            if (hipStreamWaitEvent(st, e.ready, 0) != hipSuccess) return LBF_E_HIP;
+        }
+        if (r->staged) {
+            if (hipMemcpyAsync(arena_ptr(s, r->x_off), j.x, r->x_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+                return LBF_E_HIP;
+        }
+    }
+    bool fused = blocks.size() > 1;
+    for (const lbf_block& b : blocks)
+        if (b.product == LBF_VOLTAGES || b.ctype == LBF_F32 || b.ctype != blocks[0].ctype) fused = false;
+    if (fused) return lbf_beamform_batch(blocks.data(), (int)blocks.size(), st);
+    for (const lbf_block& b : blocks) {
+        int rc = lbf_beamform(&b, st);
+        if (rc) return rc;
+    }
+    return LBF_OK;
+}
+
+void scheduler(lbf_server* s) {
+    (void)hipSetDevice(s->cfg.device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // 1. completions
+        for (size_t i = 0; i < s->inflight.size();) {
+            Launch& L = s->inflight[i];
+            hipError_t q = hipEventQuery(L.done);
+            if (q == hipErrorNotReady) { ++i; continue; }
+            const uint64_t t = now_ns();
+            for (uint64_t tk : L.tickets) {
+                auto it = s->jobs.find(tk);
+                if (it == s->jobs.end()) continue;
+                JobRec* r = it->second.get();
+                r->st.state = q == hipSuccess ? LBF_JOB_DONE : LBF_JOB_FAILED;
+                r->st.error = q == hipSuccess ? LBF_OK : LBF_E_HIP;
+                r->st.t_done_ns = t;
+                release_job(s, r);
+                s->inflight_jobs--;
+            }
+            (void)hipEventDestroy(L.done);
+            s->inflight[i] = s->inflight.back();
+            s->inflight.pop_back();
+            s->cv_done.notify_all();
+        }
+        // 2. admission (arrival order) into one batch
+        std::vector<JobRec*> batch;
+        while (!s->queue.empty() && (int)batch.size() < s->cfg.max_batch &&
+               s->inflight_jobs < s->cfg.max_inflight) {
+            auto it = s->jobs.find(s->queue.front());
+            if (it == s->jobs.end()) { s->queue.pop_front(); continue; }
+            JobRec* r = it->second.get();
+            if (!try_admit(s, r)) break;
+            r->st.state = LBF_JOB_ADMITTED;
+            r->st.t_admit_ns = now_ns();
+            s->queue.pop_front();
+            s->inflight_jobs++;
+            batch.push_back(r);
+        }
+        // 3. launch
+        if (!batch.empty()) {
+            std::vector<lbf_block> blocks;
+            std::vector<WeightEntry> went;
+            for (JobRec* r : batch) {
+                blocks.push_back(block_of(s, r));
+                went.push_back(s->wcache[r->wkey]);
+            }
+            const int si = s->next_stream;
+            s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
+            hipStream_t st = s->streams[si];
+            lk.unlock();
+            const uint64_t t0 = now_ns();
+            int rc = issue(s, batch, blocks, went, st);
+            hipEvent_t ev = nullptr;
+            if (rc == LBF_OK && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) rc = LBF_E_HIP;
+            if (rc == LBF_OK && hipEventRecord(ev, st) != hipSuccess) rc = LBF_E_HIP;
+            lk.lock();
+            if (rc != LBF_OK) {
+                // the stream may hold part of the batch: wait for it before
+                // giving the memory back
+                lk.unlock();
+                (void)hipStreamSynchronize(st);
+                lk.lock();
+                if (ev) (void)hipEventDestroy(ev);
+                for (JobRec* r : batch) {
+                    r->st.state = LBF_JOB_FAILED;
+                    r->st.error = rc;
+                    r->st.t_done_ns = now_ns();
+                    release_job(s, r);
+                    s->inflight_jobs--;
+                }
+                // weights this batch was to compute are not valid: drop them
+                for (JobRec* r : batch) {
+                    if (!r->new_weights) continue;
+                    auto it = s->wcache.find(r->wkey);
+                    if (it == s->wcache.end() || it->second.refs > 0) continue;
+                    (void)hipEventDestroy(it->second.ready);
+                    s->arena.release(it->second.off, it->second.bytes);
+                    s->wcache.erase(it);
+                }
+                s->cv_done.notify_all();
+            } else {
+                Launch L;
+                L.done = ev;
+                L.stream = si;
+                for (JobRec* r : batch) {
+                    r->st.state = LBF_JOB_RUNNING;
+                    r->st.t_start_ns = t0;
+                    r->st.batch_size = (int)batch.size();
+                    L.tickets.push_back(r->ticket);
+                }
+                s->inflight.push_back(L);
+            }
+            continue;
+        }
+        if (s->stop && s->queue.empty() && s->inflight.empty()) break;
+        if (s->inflight.empty()) s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+        else {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbf_server_create(const lbf_server_cfg* cfg, lbf_server** out) {
+    using lbf::set_error;
+    if (!cfg || !out) return set_error(LBF_E_INVAL, "lbf_server_create: NULL argument");
+    if (!cfg->d_arena || cfg->arena_bytes == 0 || cfg->max_inflight < 1 || cfg->n_streams < 1 ||
+        cfg->queue_capacity < 1 || cfg->max_batch < 1 || cfg->max_batch > LBF_MAX_BATCH || cfg->device < 0)
+        return set_error(LBF_E_INVAL, "lbf_server_create: malformed configuration");
+    std::unique_ptr<lbf_server> s(new lbf_server());
+    s->cfg = *cfg;
+    s->arena.reset(cfg->arena_bytes);
+    if (hipSetDevice(cfg->device) != hipSuccess) return set_error(LBF_E_HIP, "lbf_server_create: hipSetDevice failed");
+    for (int i = 0; i < cfg->n_streams; ++i) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+            return set_error(LBF_E_HIP, "lbf_server_create: stream creation failed");
+        }
+        s->streams.push_back(st);
+    }
+    lbf_server* raw = s.release();
+    raw->worker = std::thread(scheduler, raw);
+    *out = raw;
+    return LBF_OK;
+}
+
+int lbf_server_submit(lbf_server* s, const lbf_job* job, uint64_t* ticket) {
+    using lbf::set_error;
+    if (!s || !ticket) return set_error(LBF_E_INVAL, "lbf_server_submit: NULL argument");
+    int rc = validate_job(job);
+    if (rc) return rc;
+    if (weights_alloc_bytes(*job) + staging_bytes(*job) > s->cfg.arena_bytes)
+        return set_error(LBF_E_NOMEM, "lbf_server_submit: job footprint exceeds the arena");
+    std::unique_ptr<JobRec> r(new JobRec());
+    r->job = *job;
+    r->pos.assign(job->station_xyz, job->station_xyz + (size_t)job->S * 3);
+    r->dir.assign(job->beam_dir, job->beam_dir + (size_t)job->B * 3);
+    r->freq.assign(job->freq_hz, job->freq_hz + job->C);
+    if (job->ref_dir) {
+        memcpy(r->ref, job->ref_dir, sizeof(r->ref));
+        r->has_ref = true;
+    }
+    r->job.station_xyz = nullptr;
+    r->job.beam_dir = nullptr;
+    r->job.freq_hz = nullptr;
+    r->job.ref_dir = nullptr;
+    memset(&r->st, 0, sizeof(r->st));
+    r->st.state = LBF_JOB_QUEUED;
+    r->st.t_submit_ns = now_ns();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return set_error(LBF_E_INVAL, "lbf_server_submit: server is shutting down");
+    if ((int)s->queue.size() >= s->cfg.queue_capacity) return set_error(LBF_E_BUSY, "lbf_server_submit: queue full");
+    const uint64_t t = s->next_ticket++;
+    r->ticket = t;
+    s->jobs[t] = std::move(r);
+    s->queue.push_back(t);
+    *ticket = t;
+    s->cv_work.notify_one();
+    return LBF_OK;
+}
+
+int lbf_server_poll(lbf_server* s, uint64_t ticket, lbf_job_status* st) {
+    if (!s || !st) return LBF_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return lbf::set_error(LBF_E_NOTFOUND, "lbf_server_poll: unknown ticket");
+    *st = it->second->st;
+    return LBF_OK;
+}
+
+int lbf_server_wait(lbf_server* s, uint64_t ticket, int timeout_ms, lbf_job_status* st) {
+    if (!s || !st) return LBF_E_INVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms);
+    for (;;) {
+        auto it = s->jobs.find(ticket);
+        if (it == s->jobs.end()) return LBF_E_NOTFOUND;
+        const int state = it->second->st.state;
+        if (state == LBF_JOB_DONE || state == LBF_JOB_FAILED) {
+            *st = it->second->st;
+            return LBF_OK;
+        }
+        if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+            auto it2 = s->jobs.find(ticket);
+            if (it2 == s->jobs.end()) return LBF_E_NOTFOUND;
+            *st = it2->second->st;
+            return (st->state == LBF_JOB_DONE || st->state == LBF_JOB_FAILED) ? LBF_OK : LBF_E_BUSY;
+        }
+    }
+}
+
+int lbf_server_release(lbf_server* s, uint64_t ticket) {
+    if (!s) return LBF_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return LBF_E_NOTFOUND;
+    const int state = it->second->st.state;
+    if (state != LBF_JOB_DONE && state != LBF_JOB_FAILED) return LBF_E_BUSY;
+    s->jobs.erase(it);
+    return LBF_OK;
+}
+
+int lbf_server_destroy(lbf_server* s) {
+    if (!s) return LBF_E_INVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    for (auto& kv : s->wcache) (void)hipEventDestroy(kv.second.ready);
+    for (hipStream_t st : s->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    delete s;
+    return LBF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,291 @@
+"""Python binding of liblbf (ctypes).  Argument marshalling only: every step of
+the beam former runs in the HIP kernels of liblbf.so; torch provides device
+memory and streams.  If the library has not been built, importing works but
+every call raises ``LbfUnavailable`` -- there is no fallback.
+
+Names mirror include/lbf.h (``lbf_beamform`` -> ``beamform`` ...).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbf.so")
+
+# enums (include/lbf.h)
+OK, E_INVAL, E_UNSUPPORTED, E_NOMEM, E_HIP, E_BUSY, E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6
+CI8, CI16, CF32 = 0, 1, 2
+F32, F16, BF16 = 0, 1, 2
+VOLTAGES, STOKES_I, STOKES_IQUV = 0, 1, 4
+MAX_BATCH = 32
+JOB_QUEUED, JOB_ADMITTED, JOB_RUNNING, JOB_DONE, JOB_FAILED = range(5)
+XTYPE_NAMES = {"ci8": CI8, "ci16": CI16, "cf32": CF32}
+CTYPE_NAMES = {"f32": F32, "f16": F16, "bf16": BF16}
+PRODUCT_NAMES = {"voltages": VOLTAGES, "I": STOKES_I, "IQUV": STOKES_IQUV}
+
+
+class LbfUnavailable(RuntimeError):
+    pass
+
+
+class LbfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("lbf error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Block(ctypes.Structure):
+    _fields_ = [("d_x", ctypes.c_void_p), ("xtype", ctypes.c_int), ("S", ctypes.c_int), ("C", ctypes.c_int),
+                ("T", ctypes.c_int), ("d_w", ctypes.c_void_p), ("ctype", ctypes.c_int), ("B", ctypes.c_int),
+                ("product", ctypes.c_int), ("t_int", ctypes.c_int), ("f_int", ctypes.c_int),
+                ("d_out", ctypes.c_void_p)]
+
+
+class BlockSizes(ctypes.Structure):
+    _fields_ = [("input_bytes", ctypes.c_uint64), ("weight_bytes", ctypes.c_uint64),
+                ("output_bytes", ctypes.c_uint64), ("flops", ctypes.c_double)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int),
+                ("n_streams", ctypes.c_int), ("queue_capacity", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("device", ctypes.c_int)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("obs_id", ctypes.c_uint64),
+                ("station_xyz", ctypes.c_void_p), ("S", ctypes.c_int),
+                ("beam_dir", ctypes.c_void_p), ("B", ctypes.c_int),
+                ("ref_dir", ctypes.c_void_p),
+                ("freq_hz", ctypes.c_void_p), ("C", ctypes.c_int),
+                ("x", ctypes.c_void_p), ("xtype", ctypes.c_int), ("T", ctypes.c_int),
+                ("x_on_host", ctypes.c_int),
+                ("ctype", ctypes.c_int), ("product", ctypes.c_int), ("t_int", ctypes.c_int), ("f_int", ctypes.c_int),
+                ("d_out", ctypes.c_void_p)]
+
+
+class JobStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("error", ctypes.c_int), ("t_submit_ns", ctypes.c_uint64),
+                ("t_admit_ns", ctypes.c_uint64), ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
+                ("batch_size", ctypes.c_int)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+_PROTOS = {
+    "lbf_last_error": (ctypes.c_char_p, []),
+    "lbf_version": (ctypes.c_char_p, []),
+    "lbf_compute_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbf_beamform": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
+    "lbf_beamform_batch": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.c_void_p]),
+    "lbf_stokes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbf_transpose": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbf_incoherent": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbf_block_footprint": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.POINTER(BlockSizes)]),
+    "lbf_server_create": (ctypes.c_int, [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
+    "lbf_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]),
+    "lbf_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(JobStatus)]),
+    "lbf_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(JobStatus)]),
+    "lbf_server_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "lbf_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+}
+
+
+def lib():
+    """The loaded liblbf.so; raises LbfUnavailable if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise LbfUnavailable("liblbf.so is not built (%s); run `python -m paper_1105_0661_amd.build`"
+                                     % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _PROTOS.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LbfError(rc, lib().lbf_last_error().decode())
+
+
+def version() -> str:
+    return lib().lbf_version().decode()
+
+
+# --------------------------------------------------------------------------
+# torch marshalling helpers
+# --------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, name):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def xtype_of(x) -> int:
+    torch = _torch()
+    m = {torch.int8: CI8, torch.int16: CI16, torch.float32: CF32}
+    if x.dtype not in m:
+        raise TypeError("station samples must be int8, int16 or float32 (got %s)" % x.dtype)
+    return m[x.dtype]
+
+
+def ctype_of(w) -> int:
+    torch = _torch()
+    m = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+    if w.dtype not in m:
+        raise TypeError("weights must be float32, float16 or bfloat16 pairs (got %s)" % w.dtype)
+    return m[w.dtype]
+
+
+def weight_dtype(ctype: int):
+    torch = _torch()
+    return {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}[ctype]
+
+
+def n_stokes(product: int) -> int:
+    return {STOKES_I: 1, STOKES_IQUV: 4}[product]
+
+
+def output_shape(product: int, S: int, C: int, T: int, B: int, t_int: int = 1, f_int: int = 1):
+    if product == VOLTAGES:
+        return (C, B, T, 2, 2)
+    return (B, n_stokes(product), T // t_int, C // f_int)
+
+
+# --------------------------------------------------------------------------
+# entry points
+# --------------------------------------------------------------------------
+
+def compute_weights(station_xyz, beam_dir, freq_hz, wtype: int = F32, ref_dir=None, out=None, tau=None,
+                    stream=None):
+    """w[C][B][S] (complex as a trailing pair axis) from device f64 geometry."""
+    torch = _torch()
+    S, B, C = station_xyz.shape[0], beam_dir.shape[0], freq_hz.shape[0]
+    if out is None:
+        out = torch.empty((C, B, S, 2), dtype=weight_dtype(wtype), device=station_xyz.device)
+    ref = None
+    if ref_dir is not None:
+        ref = (ctypes.c_double * 3)(*[float(v) for v in ref_dir])
+    _check(lib().lbf_compute_weights(_dev_ptr(station_xyz, "station_xyz"), S, _dev_ptr(beam_dir, "beam_dir"), B,
+                                     ref, _dev_ptr(freq_hz, "freq_hz"), C, wtype, _dev_ptr(out, "out"),
+                                     _dev_ptr(tau, "tau"), _stream(stream)))
+    return out
+
+
+def make_block(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None) -> Block:
+    S, C, T = x.shape[0], x.shape[1], x.shape[2]
+    B = w.shape[1]
+    return Block(d_x=_dev_ptr(x, "x"), xtype=xtype_of(x), S=S, C=C, T=T, d_w=_dev_ptr(w, "w"),
+                 ctype=ctype_of(w), B=B, product=product, t_int=t_int, f_int=f_int,
+                 d_out=_dev_ptr(out, "out") if out is not None else None)
+
+
+def beamform(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, stream=None):
+    """x [S][C][T][2][2] (int8/int16/float32), w [C][B][S][2] -> voltages
+    [C][B][T][2][2] f32, or Stokes [B][K][T'][C'] f32."""
+    torch = _torch()
+    S, C, T = x.shape[0], x.shape[1], x.shape[2]
+    B = w.shape[1]
+    if out is None:
+        out = torch.empty(output_shape(product, S, C, T, B, t_int, f_int), dtype=torch.float32, device=x.device)
+    blk = make_block(x, w, product, t_int, f_int, out)
+    _check(lib().lbf_beamform(ctypes.byref(blk), _stream(stream)))
+    return out
+
+
+def beamform_batch(items: Sequence[tuple], stream=None) -> List:
+    """items: (x, w, product, t_int, f_int[, out]) tuples -> list of outputs."""
+    torch = _torch()
+    n = len(items)
+    arr = (Block * max(n, 1))()
+    outs = []
+    for i, it in enumerate(items):
+        x, w, product, t_int, f_int = it[:5]
+        out = it[5] if len(it) > 5 else None
+        if out is None:
+            S, C, T = x.shape[:3]
+            out = torch.empty(output_shape(product, S, C, T, w.shape[1], t_int, f_int), dtype=torch.float32,
+                              device=x.device)
+        outs.append(out)
+        arr[i] = make_block(x, w, product, t_int, f_int, out)
+    _check(lib().lbf_beamform_batch(arr, n, _stream(stream)))
+    return outs
+
+
+def stokes(y, product: int, t_int: int = 1, f_int: int = 1, out=None, stream=None):
+    """y [C][B][T][2][2] f32 -> s [C'][B][T'][K] f32 (unfused path)."""
+    torch = _torch()
+    C, B, T = y.shape[:3]
+    if out is None:
+        out = torch.empty((C // f_int, B, T // t_int, n_stokes(product)), dtype=torch.float32, device=y.device)
+    _check(lib().lbf_stokes(_dev_ptr(y, "y"), B, C, T, product, t_int, f_int, _dev_ptr(out, "out"),
+                            _stream(stream)))
+    return out
+
+
+def transpose(inp, out=None, stream=None):
+    """[C2][B][T2][K] f32 -> [B][K][T2][C2]; a trailing pair axis of 2 means complex elements."""
+    torch = _torch()
+    if inp.dim() == 5:
+        C2, B, T2, K, _ = inp.shape
+        elem, shape = 8, (B, K, T2, C2, 2)
+    else:
+        C2, B, T2, K = inp.shape
+        elem, shape = 4, (B, K, T2, C2)
+    if out is None:
+        out = torch.empty(shape, dtype=inp.dtype, device=inp.device)
+    _check(lib().lbf_transpose(_dev_ptr(inp, "inp"), C2, B, T2, K, elem, _dev_ptr(out, "out"), _stream(stream)))
+    return out
+
+
+def incoherent(x, product: int, t_int: int = 1, f_int: int = 1, out=None, stream=None):
+    """Incoherent beam [K][T'][C'] f32 of x [S][C][T][2][2]."""
+    torch = _torch()
+    S, C, T = x.shape[:3]
+    if out is None:
+        out = torch.empty((n_stokes(product), T // t_int, C // f_int), dtype=torch.float32, device=x.device)
+    _check(lib().lbf_incoherent(_dev_ptr(x, "x"), xtype_of(x), S, C, T, product, t_int, f_int,
+                                _dev_ptr(out, "out"), _stream(stream)))
+    return out
+
+
+def block_footprint(S: int, C: int, T: int, B: int, xtype: int, ctype: int, product: int, t_int: int = 1,
+                    f_int: int = 1) -> BlockSizes:
+    blk = Block(d_x=None, xtype=xtype, S=S, C=C, T=T, d_w=None, ctype=ctype, B=B, product=product, t_int=t_int,
+                f_int=f_int, d_out=None)
+    out = BlockSizes()
+    _check(lib().lbf_block_footprint(ctypes.byref(blk), ctypes.byref(out)))
+    return out

@@ -1,0 +1,280 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
+
+Tolerances (norm-wise relative L2 per output array and per Stokes parameter):
+1e-5 for FP32 operands, 3e-3 for FP16/BF16 operands.  Pure data movement
+(transpose) and exactly representable cases are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1105_0661_amd import lbf, synth
+from tests._util import cplx, flush, geometry, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {lbf.F32: 1e-5, lbf.F16: 3e-3, lbf.BF16: 3e-3}
+CT_NAMES = {lbf.F32: "f32", lbf.F16: "f16", lbf.BF16: "bf16"}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _weights(blk, ctype):
+    pos, dirs, freq, ref = geometry(blk)
+    return lbf.compute_weights(pos, dirs, freq, ctype, ref_dir=ref)
+
+
+def _oracle_stokes(blk, K, t_int, f_int):
+    return orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, K, t_int, f_int, 8)
+
+
+def _check_stokes(out, ref, tol, label):
+    K = ref.shape[1]
+    for k in range(K):
+        e = relerr(out[:, k], ref[:, k])
+        assert e <= tol, "%s: Stokes %s rel err %.3g > %.1g" % (label, "IQUV"[k], e, tol)
+
+
+# --------------------------------------------------------------------------
+# weights
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
+def test_weights_match_oracle(ctype):
+    torch = _torch()
+    blk = synth.make_block(37, 45, 3, 16, 16, generate=False, tag=(1105, 661, 50))
+    flush("weights %s S=37 B=45 C=48" % CT_NAMES[ctype])
+    pos, dirs, freq, ref = geometry(blk)
+    tau = torch.empty((45, 37), dtype=torch.float64, device="cuda:0")
+    w = lbf.compute_weights(pos, dirs, freq, ctype, ref_dir=ref, tau=tau)
+    torch.cuda.synchronize()
+    tau_o = orc.delays(blk.station_xyz, blk.beam_dir, blk.ref_dir)
+    assert np.max(np.abs(tau.cpu().numpy() - tau_o)) <= 1e-15 * max(1.0, np.max(np.abs(tau_o))) + 1e-22
+    w_o = orc.weights(tau_o, blk.freq_hz)
+    g = cplx(w.float())
+    err = np.max(np.abs(g - w_o))
+    half_ulp = {lbf.F32: 2.0 ** -24, lbf.F16: 2.0 ** -11, lbf.BF16: 2.0 ** -8}[ctype]
+    assert err <= half_ulp + 1e-12, err
+    if ctype == lbf.F16:
+        # one rounding from FP64: equal to numpy's double->half rounding
+        exp = np.stack([w_o.real, w_o.imag], -1).astype(np.float16)
+        same = np.mean(w.cpu().numpy() == exp)
+        assert same >= 0.9999, same
+
+
+def test_weights_large_phase_needs_fp64():
+    # remote stations (hundreds of km) put f*tau at thousands of turns: the
+    # device FP64 reduction still matches the oracle to FP32 rounding
+    torch = _torch()
+    blk = synth.make_block(8, 6, 2, 8, 16, generate=False, tag=(1105, 661, 51), radius_m=3.0e5)
+    pos, dirs, freq, _ = geometry(blk, ref=False)
+    w = lbf.compute_weights(pos, dirs, freq, lbf.F32, ref_dir=None)
+    torch.cuda.synchronize()
+    w_o = orc.weights(orc.delays(blk.station_xyz, blk.beam_dir, None), blk.freq_hz)
+    m = np.max(np.abs(blk.freq_hz[:, None, None] * orc.delays(blk.station_xyz, blk.beam_dir, None)[None]))
+    assert m > 1000
+    assert np.max(np.abs(cplx(w) - w_o)) <= 2.0 ** -24 + 1e-9
+
+
+# --------------------------------------------------------------------------
+# the contraction: voltages
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
+@pytest.mark.parametrize("xtype", ["ci8", "ci16", "cf32"])
+def test_voltages_match_oracle(xtype, ctype):
+    torch = _torch()
+    sigma = {"ci8": 20.0, "ci16": 40.0, "cf32": 30.0}[xtype]
+    # ragged everywhere: 13 stations (not a multiple of 8), 70 beams (not of 32),
+    # 112 samples (not of 32), several channels
+    blk = synth.make_block(13, 70, 1, 5, 112, xtype, sigma, tag=(1105, 661, 52))
+    flush("voltages %s %s S=13 B=70 C=5 T=112" % (xtype, CT_NAMES[ctype]))
+    x = to_dev(blk.x)
+    w = _weights(blk, ctype)
+    y = lbf.beamform(x, w, lbf.VOLTAGES)
+    torch.cuda.synchronize()
+    ref = orc.beamform(blk.x, orc.block_weights(blk))          # [C][B][T][2]
+    e = relerr(cplx(y), ref)
+    assert e <= TOL[ctype], e
+
+
+def test_single_station_zero_delay_is_identity():
+    torch = _torch()
+    blk = synth.make_block(1, 1, 1, 4, 96, "ci16", 3000.0, tag=(1105, 661, 53))
+    x = to_dev(blk.x)
+    w = torch.zeros((4, 1, 1, 2), dtype=torch.float32, device="cuda:0")
+    w[..., 0] = 1.0
+    y = lbf.beamform(x, w, lbf.VOLTAGES)
+    torch.cuda.synchronize()
+    assert np.array_equal(y[:, 0].cpu().numpy(), blk.x[0].astype(np.float32))
+
+
+def test_stations_over_one_chunk_and_several_beam_groups():
+    torch = _torch()
+    blk = synth.make_block(100, 300, 1, 2, 64, "ci8", 12.0, tag=(1105, 661, 54))
+    ref = orc.beamform(blk.x, orc.block_weights(blk))
+    x = to_dev(blk.x)
+    for ct in (lbf.F32, lbf.F16):
+        flush("voltages S=100 B=300 %s" % CT_NAMES[ct])
+        y = lbf.beamform(x, _weights(blk, ct), lbf.VOLTAGES)
+        torch.cuda.synchronize()
+        assert relerr(cplx(y), ref) <= TOL[ct]
+
+
+# --------------------------------------------------------------------------
+# fused Stokes + integration + beam-major order
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
+@pytest.mark.parametrize("product,t_int,f_int", [
+    (lbf.STOKES_I, 1, 1), (lbf.STOKES_I, 16, 1), (lbf.STOKES_IQUV, 16, 1), (lbf.STOKES_IQUV, 2, 2),
+    (lbf.STOKES_IQUV, 4, 1), (lbf.STOKES_I, 8, 5), (lbf.STOKES_IQUV, 32, 1), (lbf.STOKES_I, 64, 1),
+])
+def test_fused_stokes_match_oracle(ctype, product, t_int, f_int):
+    torch = _torch()
+    xtype = "ci8" if ctype == lbf.BF16 else "ci16"
+    blk = synth.make_block(11, 40, 2, 5, 128, xtype, 16.0 if xtype == "ci8" else 40.0, tag=(1105, 661, 55))
+    flush("fused %s K=%d t_int=%d f_int=%d" % (CT_NAMES[ctype], product, t_int, f_int))
+    x = to_dev(blk.x)
+    out = lbf.beamform(x, _weights(blk, ctype), product, t_int, f_int)
+    torch.cuda.synchronize()
+    ref = _oracle_stokes(blk, product, t_int, f_int)
+    assert out.shape == ref.shape
+    _check_stokes(out.cpu().numpy(), ref, TOL[ctype], "fused")
+
+
+def test_unfused_chain_matches_oracle_and_fused():
+    torch = _torch()
+    blk = synth.make_block(9, 35, 2, 4, 96, "ci16", 50.0, tag=(1105, 661, 56))
+    x = to_dev(blk.x)
+    w = _weights(blk, lbf.F32)
+    y = lbf.beamform(x, w, lbf.VOLTAGES)
+    s = lbf.stokes(y, lbf.STOKES_IQUV, 8, 2)                   # [C'][B][T'][K]
+    o = lbf.transpose(s)                                        # [B][K][T'][C']
+    fused = lbf.beamform(x, w, lbf.STOKES_IQUV, 8, 2)
+    torch.cuda.synchronize()
+    ref = _oracle_stokes(blk, 4, 8, 2)
+    _check_stokes(o.cpu().numpy(), ref, 1e-5, "unfused")
+    _check_stokes(fused.cpu().numpy(), o.cpu().numpy(), 1e-5, "fused vs unfused")
+    # lbf_stokes accepts any divisor, also where the fused path does not
+    s3 = lbf.stokes(y, lbf.STOKES_I, 3, 1)
+    torch.cuda.synchronize()
+    ref3 = orc.integrate(orc.stokes(orc.beamform(blk.x, orc.block_weights(blk))), 1, 3, 1)
+    assert relerr(s3.cpu().numpy(), ref3) <= 1e-5
+    with pytest.raises(lbf.LbfError) as ei:
+        lbf.beamform(x, w, lbf.STOKES_I, 3, 1)
+    assert ei.value.code == lbf.E_UNSUPPORTED
+
+
+def test_transpose_is_exact():
+    torch = _torch()
+    g = torch.Generator(device="cuda:0").manual_seed(3)
+    a = torch.randn((37, 5, 9, 4), device="cuda:0", generator=g)
+    o = lbf.transpose(a)
+    v = torch.randn((33, 3, 70, 2, 2), device="cuda:0", generator=g)
+    ov = lbf.transpose(v)
+    torch.cuda.synchronize()
+    assert torch.equal(o, a.permute(1, 3, 2, 0).contiguous())
+    assert torch.equal(ov, v.permute(1, 3, 2, 0, 4).contiguous())
+
+
+def test_voltages_beam_major_order_matches_oracle():
+    torch = _torch()
+    blk = synth.make_block(6, 33, 1, 3, 40, "ci8", 10.0, tag=(1105, 661, 57))
+    x = to_dev(blk.x)
+    y = lbf.beamform(x, _weights(blk, lbf.F32), lbf.VOLTAGES)
+    vb = lbf.transpose(y)                                       # [B][2][T][C][2]
+    torch.cuda.synchronize()
+    ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, 0, 1, 1, 4)
+    assert relerr(cplx(vb), ref) <= 1e-5
+
+
+def test_incoherent_beam_matches_oracle():
+    torch = _torch()
+    blk = synth.make_block(7, 1, 2, 4, 64, "ci16", 30.0, tag=(1105, 661, 58))
+    x = to_dev(blk.x)
+    out = lbf.incoherent(x, lbf.STOKES_IQUV, 8, 2)
+    torch.cuda.synchronize()
+    ref = orc.incoherent(blk.x, 4, 8, 2)                        # [C'][T'][K]
+    got = out.cpu().numpy()                                      # [K][T'][C']
+    for k in range(4):
+        assert relerr(got[k].T, ref[..., k]) <= 1e-5
+
+
+# --------------------------------------------------------------------------
+# batches: one persistent launch == separate launches, bit for bit
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ctype", [lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
+def test_batch_equals_single_launches_bitwise(ctype):
+    torch = _torch()
+    specs = [(24, 17, 2, 4, 64, "ci8", lbf.STOKES_I, 16, 1), (40, 150, 1, 8, 96, "ci16", lbf.STOKES_IQUV, 16, 2),
+             (64, 33, 3, 2, 32, "ci8", lbf.STOKES_IQUV, 32, 1), (31, 1, 1, 5, 48, "ci16", lbf.STOKES_I, 4, 1)]
+    items, singles, refs = [], [], []
+    for i, (S, B, nsb, nch, T, xt, prod, ti, fi) in enumerate(specs):
+        blk = synth.make_block(S, B, nsb, nch, T, xt, 16.0 if xt == "ci8" else 40.0, tag=(1105, 661, 60 + i))
+        x, w = to_dev(blk.x), _weights(blk, ctype)
+        items.append((x, w, prod, ti, fi))
+        singles.append(lbf.beamform(x, w, prod, ti, fi))
+        refs.append((blk, prod, ti, fi))
+    flush("batch of %d blocks %s" % (len(items), CT_NAMES[ctype]))
+    outs = lbf.beamform_batch(items)
+    torch.cuda.synchronize()
+    for o, s, (blk, prod, ti, fi) in zip(outs, singles, refs):
+        assert torch.equal(o, s)
+        _check_stokes(o.cpu().numpy(), _oracle_stokes(blk, prod, ti, fi), TOL[ctype], "batch")
+
+
+# --------------------------------------------------------------------------
+# full-size blocks, sampled channels
+# --------------------------------------------------------------------------
+
+def _sampled_channels(C, n, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(C, size=n, replace=False))
+
+
+def test_one_second_block_fp32_sampled():
+    torch = _torch()
+    blk = synth.config1()
+    flush("full one-second block FP32: S=64 B=128 C=8192 T=768 CI16 IQUV/16")
+    x = to_dev(blk.x)
+    w = _weights(blk, lbf.F32)
+    out = lbf.beamform(x, w, lbf.STOKES_IQUV, 16, 1)
+    torch.cuda.synchronize()
+    chans = _sampled_channels(blk.C, 6, 1)
+    # include the channels that hold the injected tones
+    chans = np.unique(np.concatenate([chans, [t.channel for t in blk.tones]]))
+    got = out[:, :, :, torch.from_numpy(chans).to("cuda:0")].cpu().numpy()
+    del x, w, out
+    xs = np.ascontiguousarray(blk.x[:, chans])
+    ref = orc.pipeline(xs, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz[chans], 4, 16, 1, 16)
+    _check_stokes(got, ref, 1e-5, "one-second FP32")
+
+
+@pytest.mark.parametrize("ctype", [lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
+def test_precision_block_sampled(ctype):
+    torch = _torch()
+    blk = synth.config2()
+    flush("full precision block %s: S=64 B=488 C=8192 T=768 CI8 IQUV/16" % CT_NAMES[ctype])
+    x = to_dev(blk.x)
+    w = _weights(blk, ctype)
+    out = lbf.beamform(x, w, lbf.STOKES_IQUV, 16, 1)
+    torch.cuda.synchronize()
+    chans = np.unique(np.concatenate([_sampled_channels(blk.C, 4, 2), [t.channel for t in blk.tones]]))
+    idx = torch.from_numpy(chans).to("cuda:0")
+    got = out[:, :, :, idx].cpu().numpy()
+    # voltages of the sampled channels through the same kernel (channel slice)
+    xs_np = np.ascontiguousarray(blk.x[:, chans])
+    y = lbf.beamform(to_dev(xs_np), w[idx].contiguous(), lbf.VOLTAGES)
+    torch.cuda.synchronize()
+    del x, w, out
+    ref = orc.pipeline(xs_np, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz[chans], 4, 16, 1, 16)
+    _check_stokes(got, ref, 3e-3, "precision block")
+    yo = orc.beamform(xs_np, orc.weights(orc.delays(blk.station_xyz, blk.beam_dir, blk.ref_dir), blk.freq_hz[chans]))
+    ev = relerr(cplx(y), yo)
+    flush("  voltage rel err %s: %.3g" % (CT_NAMES[ctype], ev))
+    assert ev <= 3e-3
