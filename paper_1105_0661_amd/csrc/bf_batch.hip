@@ -1,0 +1,94 @@
+// bf_batch.hip -- one persistent launch over the work items of several
+// blocks (Section 7 of Mol & Romein: independent observations processed in
+// parallel while resources allow).  Work groups pull items from a device
+// counter; each item runs exactly the worker lbf_beamform would run for it,
+// so every block's result is bitwise the same alone or in a batch.
+#include "bf_common.h"
+#include "bf_workers.h"
+
+namespace lbf {
+
+struct BatchArgs {
+    BlockDesc blk[kMaxBatch];
+    int item_start[kMaxBatch + 1];   // prefix sums of items per block
+    int nbg[kMaxBatch];
+    int n;
+};
+
+// Items of t_int = 16 Stokes blocks (the common integration) run the fast
+// workers; everything else in a batch runs the generic ones.
+template <int CT, int PR>
+LBF_INLINE void batch_item(const BlockDesc& d, int item, int nbg, uint32_t* wh) {
+    if (fast_path(d) && d.t_int == 16) {
+        if (d.xtype == XT_CI8) {
+            if (d.S <= 32) item_h_fast<XT_CI8, CT, PR, 16, 4>(d, item, nbg, wh);
+            else item_h_fast<XT_CI8, CT, PR, 16, 8>(d, item, nbg, wh);
+        } else {
+            if (d.S <= 32) item_h_fast<XT_CI16, CT, PR, 16, 4>(d, item, nbg, wh);
+            else item_h_fast<XT_CI16, CT, PR, 16, 8>(d, item, nbg, wh);
+        }
+    } else {
+        if (d.xtype == XT_CI8) item_h_generic<XT_CI8, CT, PR>(d, item, nbg, wh);
+        else if (d.xtype == XT_CI16) item_h_generic<XT_CI16, CT, PR>(d, item, nbg, wh);
+        else item_h_generic<XT_CF32, CT, PR>(d, item, nbg, wh);
+    }
+}
+
+template <int CT>
+__global__ __launch_bounds__(kThreads) void bf_batch_kernel(BatchArgs a, int* counter) {
+    __shared__ __attribute__((aligned(16))) uint32_t wh[kBeamGroup * kWRow];
+    __shared__ int next;
+    const int total = a.item_start[a.n];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        if (it >= total) break;     // every work group leaves once the list is exhausted
+        int j = 0;
+        while (j + 1 < a.n && a.item_start[j + 1] <= it) ++j;
+        const BlockDesc& d = a.blk[j];
+        if (d.product == PR_I) batch_item<CT, PR_I>(d, it - a.item_start[j], a.nbg[j], wh);
+        else batch_item<CT, PR_IQUV>(d, it - a.item_start[j], a.nbg[j], wh);
+    }
+}
+
+__global__ void fill_int_kernel(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, hipStream_t st) {
+    BatchArgs a;
+    a.n = n;
+    a.item_start[0] = 0;
+    for (int j = 0; j < n; ++j) {
+        a.blk[j] = blks[j];
+        int nbg;
+        const int items = block_items(blks[j], &nbg);
+        a.nbg[j] = nbg;
+        a.item_start[j + 1] = a.item_start[j] + items;
+    }
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, st, d_counter, 1, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // one resident work group per slot the hardware offers: the queue, not the
+    // grid, spreads the uneven items
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (blks[0].ctype == CT_F16)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bf_batch_kernel<CT_F16>, kThreads, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bf_batch_kernel<CT_BF16>, kThreads, 0);
+    if (per_cu < 1) per_cu = 1;
+    const int total = a.item_start[n];
+    const int slots = cus * per_cu;
+    const int grid = total < slots ? total : slots;
+    if (blks[0].ctype == CT_F16)
+        hipLaunchKernelGGL(bf_batch_kernel<CT_F16>, dim3(grid), dim3(kThreads), 0, st, a, d_counter);
+    else
+        hipLaunchKernelGGL(bf_batch_kernel<CT_BF16>, dim3(grid), dim3(kThreads), 0, st, a, d_counter);
+    return hipGetLastError();
+}
+
+}  // namespace lbf

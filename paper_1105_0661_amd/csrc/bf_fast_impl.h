@@ -1,0 +1,83 @@
+// bf_fast_impl.h -- kernels and launchers of the fast contraction workers,
+// instantiated per operand type in bf_fast_f32.hip / _f16.hip / _bf16.hip.
+#pragma once
+#include "bf_common.h"
+#include "bf_workers.h"
+
+namespace lbf {
+
+template <int XT, int PR, int TI>
+__global__ __launch_bounds__(kThreads) void bf_f32_fast_kernel(BlockDesc d, int nbg, int nitems) {
+    __shared__ float wl[kStationChunk * 2 * kBeamGroup];
+    item_f32_fast<XT, PR, TI>(d, xcd_remap(blockIdx.x, nitems), nbg, wl);
+}
+
+template <int XT, int CT, int PR, int TI, int NK>
+__global__ __launch_bounds__(kThreads) void bf_h_fast_kernel(BlockDesc d, int nbg, int nitems) {
+    __shared__ __attribute__((aligned(16))) uint32_t wh[kBeamGroup * kWRow];
+    item_h_fast<XT, CT, PR, TI, NK>(d, xcd_remap(blockIdx.x, nitems), nbg, wh);
+}
+
+// launch one instantiation; PR/TI/NK chosen from the block by the callers
+template <int XT, int PR, int TI>
+inline hipError_t launch_f32_k(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    hipLaunchKernelGGL((bf_f32_fast_kernel<XT, PR, TI>), dim3(n), dim3(kThreads), 0, st, d, nbg, n);
+    return hipGetLastError();
+}
+
+template <int XT, int PR>
+inline hipError_t launch_f32_pr(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    if (PR == PR_VOLT) return launch_f32_k<XT, PR, 1>(d, nbg, n, st);
+    switch (d.t_int) {
+        case 1: return launch_f32_k<XT, PR, 1>(d, nbg, n, st);
+        case 2: return launch_f32_k<XT, PR, 2>(d, nbg, n, st);
+        case 4: return launch_f32_k<XT, PR, 4>(d, nbg, n, st);
+        case 8: return launch_f32_k<XT, PR, 8>(d, nbg, n, st);
+        default: return launch_f32_k<XT, PR, 16>(d, nbg, n, st);
+    }
+}
+
+template <int XT>
+inline hipError_t launch_f32_xt(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    if (d.product == PR_VOLT) return launch_f32_pr<XT, PR_VOLT>(d, nbg, n, st);
+    if (d.product == PR_I) return launch_f32_pr<XT, PR_I>(d, nbg, n, st);
+    return launch_f32_pr<XT, PR_IQUV>(d, nbg, n, st);
+}
+
+template <int XT, int CT, int PR, int TI>
+inline hipError_t launch_h_k(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    if (d.S <= 32)
+        hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4>), dim3(n), dim3(kThreads), 0, st, d, nbg, n);
+    else
+        hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8>), dim3(n), dim3(kThreads), 0, st, d, nbg, n);
+    return hipGetLastError();
+}
+
+template <int XT, int CT, int PR>
+inline hipError_t launch_h_pr(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    if (PR == PR_VOLT) return launch_h_k<XT, CT, PR, 1>(d, nbg, n, st);
+    switch (d.t_int) {
+        case 1: return launch_h_k<XT, CT, PR, 1>(d, nbg, n, st);
+        case 2: return launch_h_k<XT, CT, PR, 2>(d, nbg, n, st);
+        case 4: return launch_h_k<XT, CT, PR, 4>(d, nbg, n, st);
+        case 8: return launch_h_k<XT, CT, PR, 8>(d, nbg, n, st);
+        default: return launch_h_k<XT, CT, PR, 16>(d, nbg, n, st);
+    }
+}
+
+template <int XT, int CT>
+inline hipError_t launch_h_xt(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    if (d.product == PR_VOLT) return launch_h_pr<XT, CT, PR_VOLT>(d, nbg, n, st);
+    if (d.product == PR_I) return launch_h_pr<XT, CT, PR_I>(d, nbg, n, st);
+    return launch_h_pr<XT, CT, PR_IQUV>(d, nbg, n, st);
+}
+
+template <int CT>
+inline hipError_t launch_fast_h(const BlockDesc& d, hipStream_t st) {
+    int nbg;
+    const int n = block_items(d, &nbg);
+    if (d.xtype == XT_CI8) return launch_h_xt<XT_CI8, CT>(d, nbg, n, st);
+    return launch_h_xt<XT_CI16, CT>(d, nbg, n, st);
+}
+
+}  // namespace lbf

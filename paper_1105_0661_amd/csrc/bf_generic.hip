@@ -1,0 +1,70 @@
+// bf_generic.hip -- contraction workers for any station count and input type
+// (stations in chunks of 64 whose weights are restaged in LDS per tile).  The
+// fast workers in bf_fast.hip cover up to 64 stations of complex int8/int16;
+// these cover the rest (more stations, complex float32 input).
+#include "bf_common.h"
+#include "bf_workers.h"
+
+namespace lbf {
+
+template <int XT, int PR>
+__global__ __launch_bounds__(kThreads) void bf_f32_generic_kernel(BlockDesc d, int nbg, int nitems) {
+    __shared__ float wl[kStationChunk * 2 * kBeamGroup];
+    item_f32_generic<XT, PR>(d, xcd_remap(blockIdx.x, nitems), nbg, wl);
+}
+
+template <int XT, int CT, int PR>
+__global__ __launch_bounds__(kThreads) void bf_h_generic_kernel(BlockDesc d, int nbg, int nitems) {
+    __shared__ __attribute__((aligned(16))) uint32_t wh[kBeamGroup * kWRow];
+    item_h_generic<XT, CT, PR>(d, xcd_remap(blockIdx.x, nitems), nbg, wh);
+}
+
+template <int XT>
+static hipError_t launch_f32(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    dim3 grid(n), block(kThreads);
+    switch (d.product) {
+        case PR_VOLT: hipLaunchKernelGGL((bf_f32_generic_kernel<XT, PR_VOLT>), grid, block, 0, st, d, nbg, n); break;
+        case PR_I: hipLaunchKernelGGL((bf_f32_generic_kernel<XT, PR_I>), grid, block, 0, st, d, nbg, n); break;
+        default: hipLaunchKernelGGL((bf_f32_generic_kernel<XT, PR_IQUV>), grid, block, 0, st, d, nbg, n); break;
+    }
+    return hipGetLastError();
+}
+
+template <int XT, int CT>
+static hipError_t launch_h(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    dim3 grid(n), block(kThreads);
+    switch (d.product) {
+        case PR_VOLT: hipLaunchKernelGGL((bf_h_generic_kernel<XT, CT, PR_VOLT>), grid, block, 0, st, d, nbg, n); break;
+        case PR_I: hipLaunchKernelGGL((bf_h_generic_kernel<XT, CT, PR_I>), grid, block, 0, st, d, nbg, n); break;
+        default: hipLaunchKernelGGL((bf_h_generic_kernel<XT, CT, PR_IQUV>), grid, block, 0, st, d, nbg, n); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_beamform_generic(const BlockDesc& d, hipStream_t st) {
+    int nbg;
+    const int n = block_items(d, &nbg);
+    if (d.ctype == CT_F32) {
+        if (d.xtype == XT_CI8) return launch_f32<XT_CI8>(d, nbg, n, st);
+        if (d.xtype == XT_CI16) return launch_f32<XT_CI16>(d, nbg, n, st);
+        return launch_f32<XT_CF32>(d, nbg, n, st);
+    }
+    if (d.ctype == CT_F16) {
+        if (d.xtype == XT_CI8) return launch_h<XT_CI8, CT_F16>(d, nbg, n, st);
+        if (d.xtype == XT_CI16) return launch_h<XT_CI16, CT_F16>(d, nbg, n, st);
+        return launch_h<XT_CF32, CT_F16>(d, nbg, n, st);
+    }
+    if (d.xtype == XT_CI8) return launch_h<XT_CI8, CT_BF16>(d, nbg, n, st);
+    if (d.xtype == XT_CI16) return launch_h<XT_CI16, CT_BF16>(d, nbg, n, st);
+    return launch_h<XT_CF32, CT_BF16>(d, nbg, n, st);
+}
+
+// lbf_beamform: the fast workers where they apply, the generic ones otherwise
+hipError_t launch_beamform(const BlockDesc& d, hipStream_t st) {
+    if (!fast_path(d)) return launch_beamform_generic(d, st);
+    if (d.ctype == CT_F32) return launch_fast_f32(d, st);
+    if (d.ctype == CT_F16) return launch_fast_f16(d, st);
+    return launch_fast_bf16(d, st);
+}
+
+}  // namespace lbf

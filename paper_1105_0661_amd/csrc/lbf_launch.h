@@ -13,6 +13,10 @@ int set_error(int code, const char* fmt, ...);
 hipError_t launch_weights(const double* pos, int S, const double* dir, int B, double rx, double ry, double rz,
                           const double* freq, int C, int wtype, void* w, double* tau, hipStream_t st);
 hipError_t launch_beamform(const BlockDesc& d, hipStream_t st);
+hipError_t launch_beamform_generic(const BlockDesc& d, hipStream_t st);
+hipError_t launch_fast_f32(const BlockDesc& d, hipStream_t st);
+hipError_t launch_fast_f16(const BlockDesc& d, hipStream_t st);
+hipError_t launch_fast_bf16(const BlockDesc& d, hipStream_t st);
 hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, hipStream_t st);
 hipError_t launch_stokes(const float* y, int B, int C, int T, int product, int t_int, int f_int, float* s,
                          hipStream_t st);

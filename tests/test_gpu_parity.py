@@ -112,6 +112,26 @@ def test_single_station_zero_delay_is_identity():
     assert np.array_equal(y[:, 0].cpu().numpy(), blk.x[0].astype(np.float32))
 
 
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
+@pytest.mark.parametrize("S,T", [(1, 32), (7, 33), (24, 96), (33, 100), (64, 64)])
+def test_fast_path_station_and_sample_edges(ctype, S, T):
+    # the fast workers pad stations to 8-station groups (zero beyond S) and
+    # clamp the rows of a ragged last sample tile
+    torch = _torch()
+    xt = "ci8" if ctype == lbf.BF16 else "ci16"
+    blk = synth.make_block(S, 37, 1, 3, T, xt, 16.0 if xt == "ci8" else 40.0, tag=(1105, 661, 59))
+    flush("fast edges %s S=%d T=%d" % (CT_NAMES[ctype], S, T))
+    x = to_dev(blk.x)
+    w = _weights(blk, ctype)
+    y = lbf.beamform(x, w, lbf.VOLTAGES)
+    ti = 1 if T % 2 else 4
+    s = lbf.beamform(x, w, lbf.STOKES_IQUV, ti, 1)
+    torch.cuda.synchronize()
+    ref = orc.beamform(blk.x, orc.block_weights(blk))
+    assert relerr(cplx(y), ref) <= TOL[ctype]
+    _check_stokes(s.cpu().numpy(), _oracle_stokes(blk, 4, ti, 1), TOL[ctype], "fast edges")
+
+
 def test_stations_over_one_chunk_and_several_beam_groups():
     torch = _torch()
     blk = synth.make_block(100, 300, 1, 2, 64, "ci8", 12.0, tag=(1105, 661, 54))
