@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     p.add_argument("--only", default="", help="comma list of paths to time: f32,f16,bf16 (profiling runs)")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--profile-precision", action="store_true",
+                   help="profiling run: time only the 488-beam block paths (no JSON line)")
     return p.parse_args()
 
 
@@ -97,6 +99,18 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     only = set(v for v in a.only.split(",") if v)
+
+    if a.profile_precision:
+        b2 = synth.config2(threads=16)
+        x2 = torch.from_numpy(b2.x).to(dev)
+        geo2 = (torch.from_numpy(b2.station_xyz).to(dev), torch.from_numpy(b2.beam_dir).to(dev),
+                torch.from_numpy(b2.freq_hz).to(dev), b2.ref_dir)
+        for name, ct in (("f16", lbf.F16), ("bf16", lbf.BF16)):
+            if only and name not in only:
+                continue
+            r = time_path(lbf, torch, x2, geo2, ct, lbf.STOKES_IQUV, 16, 1, a.steps, a.warmup)
+            log("precision %s: beam former %.3f ms" % (name, np.mean(r["beamform_ms"])))
+        return
 
     # ---------------- the one-second block ----------------
     t = time.time()

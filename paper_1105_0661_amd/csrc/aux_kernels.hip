@@ -158,6 +158,35 @@ hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int el
 }
 
 // ---------------------------------------------------------------------------
+// Beam-fastest staging s[c][m][b] -> final order out[b][m][c] (m = k*T' + t',
+// Section 4.6).  Tiles of 32 channels x 64 beams per m go through LDS: reads
+// are 256-byte runs along b, writes 128-byte runs along c.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* __restrict__ in, int C2, int M, int B,
+                                                                  float* __restrict__ out) {
+    __shared__ float tile[32][65];
+    const int b0 = blockIdx.x * 64, c0 = blockIdx.y * 32;
+    const size_t m = blockIdx.z;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;     // 64 x 4
+    for (int r = ty; r < 32; r += 4) {
+        const int c = c0 + r, b = b0 + tx;
+        if (c < C2 && b < B) tile[r][tx] = in[((size_t)c * M + m) * B + b];
+    }
+    __syncthreads();
+    const int cx = threadIdx.x & 31, by = threadIdx.x >> 5;     // 32 x 8
+    for (int r = by; r < 64; r += 8) {
+        const int b = b0 + r, c = c0 + cx;
+        if (c < C2 && b < B) out[((size_t)b * M + m) * C2 + c] = tile[cx][r];
+    }
+}
+
+hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, float* out, hipStream_t st) {
+    dim3 g((unsigned)((B + 63) / 64), (unsigned)((C2 + 31) / 32), (unsigned)M), b(256);
+    hipLaunchKernelGGL(stage_to_beam_major_kernel, g, b, 0, st, stage, C2, M, B, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Incoherent beam (Section 3): sum over stations of each station's Stokes
 // parameters, integrated like a tied-array beam.  One thread per output
 // (c', t'); loops channel, time, station; reads are along t for a station.

@@ -17,9 +17,11 @@ struct BatchArgs {
 
 // Items of t_int = 16 Stokes blocks (the common integration) run the fast
 // workers; everything else in a batch runs the generic ones.
+__host__ __device__ inline bool batch_fast(const BlockDesc& d) { return fast_path(d) && d.t_int == 16; }
+
 template <int CT, int PR>
 LBF_INLINE void batch_item(const BlockDesc& d, int item, int nbg, uint32_t* wh) {
-    if (fast_path(d) && d.t_int == 16) {
+    if (batch_fast(d)) {
         if (d.xtype == XT_CI8) {
             if (d.S <= 32) item_h_fast<XT_CI8, CT, PR, 16, 4>(d, item, nbg, wh);
             else item_h_fast<XT_CI8, CT, PR, 16, 8>(d, item, nbg, wh);
@@ -36,7 +38,7 @@ LBF_INLINE void batch_item(const BlockDesc& d, int item, int nbg, uint32_t* wh) 
 
 template <int CT>
 __global__ __launch_bounds__(kThreads) void bf_batch_kernel(BatchArgs a, int* counter) {
-    __shared__ __attribute__((aligned(16))) uint32_t wh[kBeamGroup * kWRow];
+    __shared__ __attribute__((aligned(16))) uint32_t wh[kWhWords];
     __shared__ int next;
     const int total = a.item_start[a.n];
     for (;;) {
@@ -62,16 +64,34 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
     BatchArgs a;
     a.n = n;
     a.item_start[0] = 0;
+    // fast Stokes blocks stage beam-fastest and are transposed afterwards
+    size_t stage_bytes = 0, stage_off[kMaxBatch];
+    for (int j = 0; j < n; ++j) {
+        stage_off[j] = stage_bytes;
+        if (batch_fast(blks[j])) {
+            const int K = blks[j].product == PR_IQUV ? 4 : 1;
+            stage_bytes += ((size_t)blks[j].C * K * (blks[j].T / blks[j].t_int) * blks[j].B * sizeof(float) + 255) & ~(size_t)255;
+        }
+    }
+    char* stage = nullptr;
+    if (stage_bytes) {
+        hipError_t e = hipMallocAsync((void**)&stage, stage_bytes, st);
+        if (e != hipSuccess) return e;
+    }
     for (int j = 0; j < n; ++j) {
         a.blk[j] = blks[j];
+        if (batch_fast(blks[j])) a.blk[j].out = stage + stage_off[j];
         int nbg;
-        const int items = block_items(blks[j], &nbg);
+        const int items = batch_fast(blks[j]) ? block_items_fast_h(blks[j], &nbg) : block_items(blks[j], &nbg);
         a.nbg[j] = nbg;
         a.item_start[j + 1] = a.item_start[j] + items;
     }
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, st, d_counter, 1, 0);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+        if (stage) (void)hipFreeAsync(stage, st);
+        return e;
+    }
     // one resident work group per slot the hardware offers: the queue, not the
     // grid, spreads the uneven items
     int dev = 0, cus = 256, per_cu = 1;
@@ -88,7 +108,19 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
         hipLaunchKernelGGL(bf_batch_kernel<CT_F16>, dim3(grid), dim3(kThreads), 0, st, a, d_counter);
     else
         hipLaunchKernelGGL(bf_batch_kernel<CT_BF16>, dim3(grid), dim3(kThreads), 0, st, a, d_counter);
-    return hipGetLastError();
+    e = hipGetLastError();
+    for (int j = 0; j < n && e == hipSuccess; ++j) {
+        if (!batch_fast(blks[j])) continue;
+        const BlockDesc& b = blks[j];
+        const int K = b.product == PR_IQUV ? 4 : 1;
+        e = launch_stage_to_beam_major((const float*)(stage + stage_off[j]), b.C, K * (b.T / b.t_int), b.B,
+                                       (float*)b.out, st);
+    }
+    if (stage) {
+        const hipError_t ef = hipFreeAsync(stage, st);
+        if (e == hipSuccess) e = ef;
+    }
+    return e;
 }
 
 }  // namespace lbf

@@ -24,6 +24,8 @@ constexpr int kStationChunk = 64;               // stations whose weights sit in
 constexpr int kWavesPerGroup = 4;
 constexpr int kThreads = kWave * kWavesPerGroup;
 constexpr int kWRow = kStationChunk + 4;        // LDS row of packed f16/bf16 weights (words)
+constexpr int kSuperGroup = 4 * kBeamGroup;     // beams of one fast FP16/BF16 work item
+constexpr int kWhWords = kSuperGroup * kWRow;   // their LDS weights: 136 KB
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
@@ -219,6 +221,57 @@ LBF_INLINE void stage_weights_h(uint32_t* wh, const BlockDesc& d, int c, int b0,
     }
 }
 
+// Fast-path staging (S <= 64): every thread issues all of its loads before
+// the first LDS write, so one item's weights cost about one memory latency.
+// Buffer loads over the channel's [B][S] block read beams >= B as zero;
+// stations >= S are zeroed explicitly.
+LBF_INLINE __amdgpu_buffer_rsrc_t weight_rsrc(const BlockDesc& d, int c, int bytes) {
+    const uint64_t base = reinterpret_cast<uint64_t>(d.w) + (uint64_t)c * d.B * d.S * bytes;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    const uint32_t nrec = __builtin_amdgcn_readfirstlane((uint32_t)d.B * (uint32_t)d.S * (uint32_t)bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0, (int)nrec,
+                                             0x00020000);
+}
+
+// wh[b][s] packed 16-bit complex: wave w fills rows w, w+4, ..., lane = station
+LBF_INLINE void stage_weights_h_fast(uint32_t* wh, const BlockDesc& d, int c, int b0) {
+    constexpr int R = kBeamGroup / kWavesPerGroup;   // rows per wave
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const __amdgpu_buffer_rsrc_t rs = weight_rsrc(d, c, 4);
+    const bool sok = lane < d.S;
+    uint32_t v[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int b = b0 + wave + kWavesPerGroup * k;
+        v[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(((uint32_t)b * d.S + lane) * 4u), 0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) wh[(wave + kWavesPerGroup * k) * kWRow + lane] = sok ? v[k] : 0u;
+}
+
+// wl[s][ri][b] floats: thread -> beam (bl = tid % 128), stations 2k + tid/128
+LBF_INLINE void stage_weights_f32_fast(float* wl, const BlockDesc& d, int c, int b0) {
+    constexpr int R = kStationChunk * kBeamGroup / kThreads;   // 32 per thread
+    typedef float float2v __attribute__((ext_vector_type(2)));
+    const int bl = threadIdx.x % kBeamGroup, s1 = threadIdx.x / kBeamGroup;
+    const __amdgpu_buffer_rsrc_t rs = weight_rsrc(d, c, 8);
+    const uint32_t rowoff = (uint32_t)(b0 + bl) * (uint32_t)d.S;
+    float2v v[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int sl = 2 * k + s1;
+        v[k] = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)((rowoff + sl) * 8u), 0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int sl = 2 * k + s1;
+        const bool ok = sl < d.S;
+        wl[(sl * 2 + 0) * kBeamGroup + bl] = ok ? v[k][0] : 0.f;
+        wl[(sl * 2 + 1) * kBeamGroup + bl] = ok ? v[k][1] : 0.f;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // epilogue: voltages, or Stokes + integration + beam-major store
 // ---------------------------------------------------------------------------
@@ -341,15 +394,41 @@ LBF_INLINE void epilogue_tile(const floatx16 (&acc)[4], const EpiCtx& e, int bea
     }
 }
 
-// fast workers: t_int fixed at compile time, f_int == 1 (plain stores)
+// Fast workers, Stokes: integrated parameters go to a beam-fastest staging
+// layout s[c][k][t'][b] (e.out, e.c = channel).  The 32 lanes of a lane half
+// hold 32 consecutive beams, so every store instruction writes two whole
+// 128-byte lines; the beam-major final order is produced by a separate tiled
+// transpose.  (Storing straight into [b][k][t'][c] scatters 4-byte writes
+// whose lines, a multiple of 2^19 bytes apart, all fall into one L2 set.)
+template <int PR, int TI>
+LBF_INLINE void stokes_store_bfast(const floatx16 (&acc)[4], const EpiCtx& e, int beam, int t0, int h) {
+    constexpr int K = PR == PR_IQUV ? 4 : 1;
+    constexpr int NOUT = 16 / TI;
+    const int tq0 = (t0 + 16 * h) / TI;
+    const bool bok = beam < e.B;
+    float* base = e.out + (size_t)e.c * K * e.T2 * (size_t)e.B + beam;
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        float s[4], v[4];
+        stokes_sums<PR, TI>(acc, o * TI, s);
+        stokes_from_sums<PR>(s, v);
+        const int tq = tq0 + o;
+        if (bok && tq < e.T2) {
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) base[((size_t)kk * e.T2 + tq) * e.B] = v[kk];
+        }
+    }
+}
+
+// fast workers: t_int fixed at compile time, f_int == 1
 template <int PR, int TI>
 LBF_INLINE void epilogue_tiles_fixed(const floatx16 (&acc)[kBeamTiles][4], const EpiCtx& e, int b0, int r, int t0,
                                      int h) {
-    if (PR == PR_VOLT) {
 #pragma unroll
-        for (int a = 0; a < kBeamTiles; ++a) epilogue_tile<PR>(acc[a], e, b0 + a * kTile + r, t0, h);
-    } else {
-        epilogue_tiles_ti<PR, TI, true>(acc, e, b0, r, t0, h);
+    for (int a = 0; a < kBeamTiles; ++a) {
+        if (PR == PR_VOLT) epilogue_tile<PR>(acc[a], e, b0 + a * kTile + r, t0, h);
+        else stokes_store_bfast<PR, TI>(acc[a], e, b0 + a * kTile + r, t0, h);
+        __builtin_amdgcn_sched_barrier(0);   // one beam tile's temporaries at a time
     }
 }
 
@@ -430,6 +509,12 @@ LBF_INLINE WaveTiles wave_tiles(int wave, int T, int t_int) {
     const int mine = ngroups > wave ? (ngroups - wave + kWavesPerGroup - 1) / kWavesPerGroup : 0;
     w.ntw = mine * w.tpg;
     return w;
+}
+
+// work items of the fast FP16/BF16 worker: (channel, super-group of 512 beams)
+inline int block_items_fast_h(const BlockDesc& d, int* nsg) {
+    *nsg = (d.B + kSuperGroup - 1) / kSuperGroup;
+    return d.C * *nsg;
 }
 
 // number of (channel group, beam group) work items of a block

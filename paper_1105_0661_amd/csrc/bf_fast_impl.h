@@ -13,9 +13,9 @@ __global__ __launch_bounds__(kThreads) void bf_f32_fast_kernel(BlockDesc d, int 
 }
 
 template <int XT, int CT, int PR, int TI, int NK>
-__global__ __launch_bounds__(kThreads) void bf_h_fast_kernel(BlockDesc d, int nbg, int nitems) {
-    __shared__ __attribute__((aligned(16))) uint32_t wh[kBeamGroup * kWRow];
-    item_h_fast<XT, CT, PR, TI, NK>(d, xcd_remap(blockIdx.x, nitems), nbg, wh);
+__global__ __launch_bounds__(kThreads) void bf_h_fast_kernel(BlockDesc d, int nsg, int nitems) {
+    __shared__ __attribute__((aligned(16))) uint32_t wh[kWhWords];
+    item_h_fast<XT, CT, PR, TI, NK>(d, xcd_remap(blockIdx.x, nitems), nsg, wh);
 }
 
 // launch one instantiation; PR/TI/NK chosen from the block by the callers
@@ -75,7 +75,7 @@ inline hipError_t launch_h_xt(const BlockDesc& d, int nbg, int n, hipStream_t st
 template <int CT>
 inline hipError_t launch_fast_h(const BlockDesc& d, hipStream_t st) {
     int nbg;
-    const int n = block_items(d, &nbg);
+    const int n = block_items_fast_h(d, &nbg);
     if (d.xtype == XT_CI8) return launch_h_xt<XT_CI8, CT>(d, nbg, n, st);
     return launch_h_xt<XT_CI16, CT>(d, nbg, n, st);
 }

@@ -59,12 +59,29 @@ hipError_t launch_beamform_generic(const BlockDesc& d, hipStream_t st) {
     return launch_h<XT_CF32, CT_BF16>(d, nbg, n, st);
 }
 
-// lbf_beamform: the fast workers where they apply, the generic ones otherwise
-hipError_t launch_beamform(const BlockDesc& d, hipStream_t st) {
-    if (!fast_path(d)) return launch_beamform_generic(d, st);
+static hipError_t launch_fast(const BlockDesc& d, hipStream_t st) {
     if (d.ctype == CT_F32) return launch_fast_f32(d, st);
     if (d.ctype == CT_F16) return launch_fast_f16(d, st);
     return launch_fast_bf16(d, st);
+}
+
+// lbf_beamform: the fast workers where they apply, the generic ones otherwise.
+// Fast Stokes blocks go through a beam-fastest staging buffer (stream-ordered
+// allocation) and a tiled transpose into the beam-major output.
+hipError_t launch_beamform(const BlockDesc& d, hipStream_t st) {
+    if (!fast_path(d)) return launch_beamform_generic(d, st);
+    if (d.product == PR_VOLT) return launch_fast(d, st);
+    const int K = d.product == PR_IQUV ? 4 : 1;
+    const int T2 = d.T / d.t_int;
+    void* stage = nullptr;
+    hipError_t e = hipMallocAsync(&stage, (size_t)d.C * K * T2 * d.B * sizeof(float), st);
+    if (e != hipSuccess) return e;
+    BlockDesc ds = d;
+    ds.out = stage;
+    e = launch_fast(ds, st);
+    if (e == hipSuccess) e = launch_stage_to_beam_major((const float*)stage, d.C, K * T2, d.B, (float*)d.out, st);
+    const hipError_t ef = hipFreeAsync(stage, st);
+    return e != hipSuccess ? e : ef;
 }
 
 }  // namespace lbf

@@ -43,7 +43,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* wl) 
         e.c = c;
         e.first = j == 0;
         __syncthreads();
-        stage_weights_f32(wl, d, c, b0, 0);
+        stage_weights_f32_fast(wl, d, c, b0);
         __syncthreads();
         for (int k = 0; k < wt.ntw; ++k) {
             const int t0 = wt.tile(k) * kTile;
@@ -97,34 +97,41 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* wl) 
 }
 
 // FP16/BF16 operands (MFMA 32x32x16: 8 stations per step).  NK = K-steps
-// (8-station groups) covering the stations.  The whole next tile's samples
-// are loaded into registers while the current tile computes; lane half h
-// takes stations 8kk + 4h + i of K-step kk.
+// (8-station groups) covering the stations.  A work item is one channel and
+// a super-group of up to 512 beams: the 4 waves split into BW beam groups of
+// 128 beams (weights of all of them in LDS) times 4/BW sample streams, so a
+// channel's samples are read once and the XCD-aware item order puts 32
+// adjacent channels -- one full 128-byte line of the beam-major output -- on
+// each XCD at a time.  Lane half h takes stations 8kk + 4h + i of K-step kk.
 template <int XT, int CT, int PR, int TI, int NK>
-LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* wh) {
+LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nsg, uint32_t* wh) {
     typedef Raw<XT> R;
     typedef typename R::type RT;
     typedef typename MfmaH<CT>::vec V;
     constexpr int BYTES = sizeof(RT);
-    const int g = item / nbg, bg = item % nbg;
+    const int c = item / nsg, sg = item % nsg;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int r = lane & 31, h = lane >> 5;
-    const int S = d.S, C = d.C, T = d.T;
-    const int b0 = bg * kBeamGroup;
-    const int f_int = 1;                             // fast path: no channel integration
-    EpiCtx e = make_epi(d, PR, g);
-    const WaveTiles wt = wave_tiles(wave, T, TI);
+    const int S = d.S, T = d.T;
+    const int bsg0 = sg * kSuperGroup;
+    const int nb = min(kSuperGroup, d.B - bsg0);
+    const int BW = nb <= kBeamGroup ? 1 : (nb <= 2 * kBeamGroup ? 2 : 4);
+    const int TW = kWavesPerGroup / BW;
+    const int bw = wave % BW, tw = wave / BW;
+    const int b0 = bsg0 + bw * kBeamGroup;
+    EpiCtx e = make_epi(d, PR, c);
+    e.c = c;
+    e.first = 1;
+    const int ntiles = (T + kTile - 1) / kTile;
+    const int ntw = ntiles > tw ? (ntiles - tw + TW - 1) / TW : 0;
     const int trow = tile_row_sample(r);
-    const uint32_t stride_bytes = (uint32_t)((size_t)C * T * BYTES);
+    const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
     const uint32_t hoff = (uint32_t)h * 4u * stride_bytes;
+    const int wbase = bw * kBeamGroup * kWRow;
 
-    for (int j = 0; j < f_int; ++j) {
-        const int c = g * f_int + j;
-        e.c = c;
-        e.first = j == 0;
-        __syncthreads();
-        stage_weights_h(wh, d, c, b0, 0);
-        __syncthreads();
+    for (int g = 0; g < BW; ++g) stage_weights_h_fast(wh + g * kBeamGroup * kWRow, d, c, bsg0 + g * kBeamGroup);
+    __syncthreads();
+    {
         // Rolling prefetch: slot kk holds K-step kk of the current tile until
         // it is converted, then is refilled with K-step kk of the next tile,
         // so every load has a whole tile of MFMAs to arrive.
@@ -135,16 +142,16 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* wh)
 #pragma unroll
             for (int i = 0; i < 4; ++i) buf[kk][i] = buffer_sample<XT>(rs, off + (uint32_t)i * stride_bytes);
         };
-        if (wt.ntw > 0) {
+        if (ntw > 0) {
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) load_step(wt.tile(0), kk);
+            for (int kk = 0; kk < NK; ++kk) load_step(tw, kk);
         }
-        for (int k = 0; k < wt.ntw; ++k) {
-            const int t0 = wt.tile(k) * kTile;
-            const int tnext = wt.tile(k + 1 < wt.ntw ? k + 1 : k);
+        for (int k = 0; k < ntw; ++k) {
+            const int t0 = (tw + TW * k) * kTile;
+            const int tnext = tw + TW * (k + 1 < ntw ? k + 1 : k);
             // read the weight fragments from LDS inside the tile loop: kept
             // live across tiles they would take 128 VGPRs
-            int widx = r * kWRow + 4 * h;
+            int widx = wbase + r * kWRow + 4 * h;
             __asm__ volatile("" : "+v"(widx));
             const uint32_t* wrow = wh + widx;
             floatx16 acc[kBeamTiles][4];
@@ -160,16 +167,16 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* wh)
                 const u32x4 uyi = {p[0].yi, p[1].yi, p[2].yi, p[3].yi};
                 const V axr = __builtin_bit_cast(V, uxr), axi = __builtin_bit_cast(V, uxi);
                 const V ayr = __builtin_bit_cast(V, uyr), ayi = __builtin_bit_cast(V, uyi);
-                V bw[kBeamTiles];
+                V bfr[kBeamTiles];
 #pragma unroll
                 for (int a = 0; a < kBeamTiles; ++a)
-                    bw[a] = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(wrow + a * kTile * kWRow + 8 * kk));
+                    bfr[a] = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(wrow + a * kTile * kWRow + 8 * kk));
 #pragma unroll
                 for (int a = 0; a < kBeamTiles; ++a) {
-                    acc[a][0] = MfmaH<CT>::mfma(axr, bw[a], kk == 0 ? zero16() : acc[a][0]);
-                    acc[a][1] = MfmaH<CT>::mfma(axi, bw[a], kk == 0 ? zero16() : acc[a][1]);
-                    acc[a][2] = MfmaH<CT>::mfma(ayr, bw[a], kk == 0 ? zero16() : acc[a][2]);
-                    acc[a][3] = MfmaH<CT>::mfma(ayi, bw[a], kk == 0 ? zero16() : acc[a][3]);
+                    acc[a][0] = MfmaH<CT>::mfma(axr, bfr[a], kk == 0 ? zero16() : acc[a][0]);
+                    acc[a][1] = MfmaH<CT>::mfma(axi, bfr[a], kk == 0 ? zero16() : acc[a][1]);
+                    acc[a][2] = MfmaH<CT>::mfma(ayr, bfr[a], kk == 0 ? zero16() : acc[a][2]);
+                    acc[a][3] = MfmaH<CT>::mfma(ayi, bfr[a], kk == 0 ? zero16() : acc[a][3]);
                 }
             }
             epilogue_tiles_fixed<PR, TI>(acc, e, b0, r, t0, h);
