@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--profile-precision", action="store_true",
                    help="profiling run: time only the 488-beam block paths (no JSON line)")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="counter calibration run: three plain 1 GiB device-to-device copies (no JSON line)")
     return p.parse_args()
 
 
@@ -99,6 +101,16 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     only = set(v for v in a.only.split(",") if v)
+
+    if a.copy_calibration:
+        n = 1 << 28                                  # 1 GiB of float32
+        src = torch.ones(n, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d bytes three times" % (4 * n))
+        return
 
     if a.profile_precision:
         b2 = synth.config2(threads=16)
