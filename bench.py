@@ -59,15 +59,21 @@ def relerr(g, o):
 
 
 def time_path(lbf, torch, x, geo, ctype, product, t_int, f_int, steps, warmup):
-    """Time `steps` blocks of weights + fused beam former on torch's current
-    stream; returns per-step ms, per-kernel ms and the last output."""
+    """Time `steps` blocks through the whole path on torch's current stream:
+    FP64 weights (lbf_compute_weights), the contraction kernel with fused Stokes
+    and integration (lbf_beamform_channel_major, one kernel launch) and the
+    reorder into the beam-major final order (lbf_beam_major).  HIP events on
+    that stream bracket each call.  Returns per-step and per-call ms and the
+    beam-major output of the last step."""
     pos, dirs, freq, ref = geo
     S, C, T = x.shape[:3]
     B = dirs.shape[0]
     w = torch.empty((C, B, S, 2), dtype=lbf.weight_dtype(ctype), device=x.device)
+    cm = torch.empty(lbf.output_shape(product, S, C, T, B, t_int, f_int, channel_major=True), dtype=torch.float32,
+                     device=x.device)
     out = torch.empty(lbf.output_shape(product, S, C, T, B, t_int, f_int), dtype=torch.float32, device=x.device)
     n = warmup + steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n)]
     torch.cuda.synchronize()
     t0 = None
     for i in range(n):
@@ -77,14 +83,48 @@ def time_path(lbf, torch, x, geo, ctype, product, t_int, f_int, steps, warmup):
         ev[i][0].record()
         lbf.compute_weights(pos, dirs, freq, ctype, ref_dir=ref, out=w)
         ev[i][1].record()
-        lbf.beamform(x, w, product, t_int, f_int, out=out)
+        lbf.beamform_channel_major(x, w, product, t_int, f_int, out=cm)
         ev[i][2].record()
+        lbf.beam_major(cm, out=out)
+        ev[i][3].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    step_ms = np.array([ev[i][0].elapsed_time(ev[i][2]) for i in range(warmup, n)])
-    w_ms = np.array([ev[i][0].elapsed_time(ev[i][1]) for i in range(warmup, n)])
-    bf_ms = np.array([ev[i][1].elapsed_time(ev[i][2]) for i in range(warmup, n)])
-    return dict(wall_s=wall, step_ms=step_ms, weights_ms=w_ms, beamform_ms=bf_ms, out=out, w=w)
+
+    def span(a, b):
+        return np.array([ev[i][a].elapsed_time(ev[i][b]) for i in range(warmup, n)])
+
+    return dict(wall_s=wall, step_ms=span(0, 3), weights_ms=span(0, 1), beamform_ms=span(1, 2),
+                reorder_ms=span(2, 3), out=out, w=w)
+
+
+KERNEL_SOURCES = ["lbf_device.h", "bf_common.h", "bf_workers.h", "bf_fast_impl.h", "bf_fast_f32.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_one_second_fp32.txt")
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the FP32 contraction kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1105_0661_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 contraction kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain
+    device copy), or None if the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if line.startswith("TRAFFIC "):
+                    kv = dict(t.split("=", 1) for t in line.split()[1:])
+                    if kv.get("sources") == kernel_source_hash():
+                        return float(kv["read_bytes"]) + float(kv["write_bytes"])
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -143,9 +183,9 @@ def main():
         if only and name not in only:
             continue
         r = time_path(lbf, torch, x, geo, ct, prod, t_int, f_int, a.steps, a.warmup)
-        log("%s: step %.3f ms (weights %.3f, beam former %.3f)" % (name, np.median(r["step_ms"]),
-                                                                   np.median(r["weights_ms"]),
-                                                                   np.median(r["beamform_ms"])))
+        log("%s: step %.3f ms (weights %.3f, contraction %.3f, reorder %.3f)" % (
+            name, np.median(r["step_ms"]), np.median(r["weights_ms"]), np.median(r["beamform_ms"]),
+            np.median(r["reorder_ms"])))
         res[name] = r
 
     # ---------------- oracle on sampled subbands (CPU baseline + errors) ----------------
@@ -194,7 +234,9 @@ def main():
             r = time_path(lbf, torch, x2, geo2, ct, prod, t_int, f_int, max(5, a.steps // 2), a.warmup)
             kms = float(np.mean(r["beamform_ms"]))
             extra[name] = {"beam_samples_per_s": b2.B * b2.C * b2.T / (np.median(r["step_ms"]) / 1e3),
-                           "ms_per_step": float(np.median(r["step_ms"])), "beamform_kernel_ms": kms,
+                           "ms_per_step": float(np.median(r["step_ms"])), "contraction_kernel_ms": kms,
+                           "reorder_kernel_ms": float(np.mean(r["reorder_ms"])),
+                           "weights_kernel_ms": float(np.mean(r["weights_ms"])),
                            "mfma_TFLOPs": fp2.flops / (kms / 1e3) / 1e12,
                            "mfma_frac": fp2.flops / (kms / 1e3) / 1e12 / PEAK["f16_TFLOPs"]}
             log("precision %s: %s" % (name, extra[name]))
@@ -207,6 +249,7 @@ def main():
     kms = float(np.mean(r["beamform_ms"]))
     flops = fp.flops
     achieved = flops / (kms / 1e3) / 1e12
+    alg_bytes = fp.input_bytes + fp.weight_bytes + fp.output_bytes
     line = {
         "metric": "tied-array beam-samples/s, FP16-MFMA vs FP32 at <=3e-3 rel err; p99 block latency",
         "value": bsamp / (ms / 1e3),
@@ -219,24 +262,30 @@ def main():
         "config": {"workload": "one-second block: 64 stations, 32 subbands x 256 channels, 768 samples, complex "
                                "int16, 128 beams, Stokes IQUV integrated x16, beam-major f32 out",
                    "S": S, "C": C, "T": T, "B": B, "xtype": "ci16", "product": "IQUV", "t_int": t_int,
-                   "f_int": f_int, "step": "lbf_compute_weights + lbf_beamform (fused)"},
+                   "f_int": f_int,
+                   "step": "lbf_compute_weights + lbf_beamform_channel_major (fused contraction, Stokes, "
+                           "integration) + lbf_beam_major (final order)"},
         "p50_block_latency_ms": float(np.percentile(r["step_ms"], 50)),
         "p99_block_latency_ms": float(np.percentile(r["step_ms"], 99)),
         "input_Gbps_equiv": fp.input_bytes * 8 / (ms / 1e3) / 1e9,
         "realtime_factor": block_seconds / (ms / 1e3),
         "TFLOPs": flops / (ms / 1e3) / 1e12,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32_TFLOPs"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f32_TFLOPs"], "traffic": None,
-                     "kernel": "bf_f32_kernel<CI16, IQUV>", "kernel_ms": kms,
-                     "algorithmic_flops_per_launch": flops},
+                     "frac": achieved / PEAK["f32_TFLOPs"],
+                     "traffic": measured_traffic() if main_name == "f32" else None,
+                     "kernel": "bf_f32_fast_kernel<ci16, IQUV, t_int 16>", "kernel_ms": kms,
+                     "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel_sources": kernel_source_hash()},
         "cpu_baseline": cpu,
     }
     paths = {}
     for name, rr in res.items():
         m = float(np.median(rr["step_ms"]))
         k = float(np.mean(rr["beamform_ms"]))
-        ent = {"beam_samples_per_s": bsamp / (m / 1e3), "ms_per_step": m, "beamform_kernel_ms": k,
-               "weights_kernel_ms": float(np.mean(rr["weights_ms"])),
+        ro = float(np.mean(rr["reorder_ms"]))
+        ent = {"beam_samples_per_s": bsamp / (m / 1e3), "ms_per_step": m, "contraction_kernel_ms": k,
+               "weights_kernel_ms": float(np.mean(rr["weights_ms"])), "reorder_kernel_ms": ro,
+               "reorder_hbm_GBps": 2 * fp.output_bytes / (ro / 1e3) / 1e9,
                "p99_block_latency_ms": float(np.percentile(rr["step_ms"], 99)),
                "rel_err_vs_oracle": errs.get(name)}
         if name != "f32":

@@ -76,6 +76,7 @@ lbf::BlockDesc to_desc(const lbf_block* b) {
     d.xtype = b->xtype; d.ctype = b->ctype; d.product = b->product;
     d.t_int = b->product == LBF_VOLTAGES ? 1 : b->t_int;
     d.f_int = b->product == LBF_VOLTAGES ? 1 : b->f_int;
+    d.order = 0;
     return d;
 }
 
@@ -137,6 +138,31 @@ int lbf_beamform(const lbf_block* blk, void* stream) {
     if (rc) return rc;
     hipError_t e = lbf::launch_beamform(to_desc(blk), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lbf_beamform");
+    return ok();
+}
+
+int lbf_beamform_channel_major(const lbf_block* blk, void* stream) {
+    int rc = check_block(blk, "lbf_beamform_channel_major");
+    if (rc) return rc;
+    lbf::BlockDesc d = to_desc(blk);
+    d.order = 1;
+    hipError_t e = lbf::launch_beamform(d, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_beamform_channel_major");
+    return ok();
+}
+
+int lbf_beam_major(const float* d_in, int C2, int K, int T2, int B, float* d_out, void* stream) {
+    if (C2 < 1 || T2 < 1 || B < 1) return fail(LBF_E_INVAL, "lbf_beam_major: sizes must be >= 1");
+    if (K != 1 && K != 4) return fail(LBF_E_INVAL, "lbf_beam_major: K must be 1 or 4 (got %d)", K);
+    if (!d_in || !d_out) return fail(LBF_E_INVAL, "lbf_beam_major: NULL device pointer");
+    const size_t bytes = (size_t)C2 * K * T2 * B * sizeof(float);
+    const char* a = (const char*)d_in;
+    const char* b = (const char*)d_out;
+    if (a < b + bytes && b < a + bytes) return fail(LBF_E_INVAL, "lbf_beam_major: input and output overlap");
+    if ((long long)K * T2 > 0x7fffffffLL || C2 > (1 << 26) || B > (1 << 26))
+        return fail(LBF_E_INVAL, "lbf_beam_major: too large");
+    hipError_t e = lbf::launch_stage_to_beam_major(d_in, C2, K * T2, B, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_beam_major");
     return ok();
 }
 

@@ -165,8 +165,8 @@ hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int el
 __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* __restrict__ in, int C2, int M, int B,
                                                                   float* __restrict__ out) {
     __shared__ float tile[32][65];
-    const int b0 = blockIdx.x * 64, c0 = blockIdx.y * 32;
-    const size_t m = blockIdx.z;
+    const int b0 = blockIdx.z * 64, c0 = blockIdx.y * 32;
+    const size_t m = blockIdx.x;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;     // 64 x 4
     for (int r = ty; r < 32; r += 4) {
         const int c = c0 + r, b = b0 + tx;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* _
 }
 
 hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, float* out, hipStream_t st) {
-    dim3 g((unsigned)((B + 63) / 64), (unsigned)((C2 + 31) / 32), (unsigned)M), b(256);
+    dim3 g((unsigned)M, (unsigned)((C2 + 31) / 32), (unsigned)((B + 63) / 64)), b(256);
     hipLaunchKernelGGL(stage_to_beam_major_kernel, g, b, 0, st, stage, C2, M, B, out);
     return hipGetLastError();
 }

@@ -282,6 +282,7 @@ struct EpiCtx {
     int g;          // output channel c' (Stokes)
     int first;      // first channel of the f_int group: store, else accumulate
     int t_int;
+    size_t sb, sk, st, sc;   // Stokes element strides of beam, parameter, t' and c'
 };
 
 LBF_INLINE void store_or_add(float* p, float v, int first) {
@@ -332,7 +333,7 @@ LBF_INLINE void stokes_store_ti(const floatx16 (&acc)[4], const EpiCtx& e, int b
     constexpr int NOUT = 16 / TI;
     const int tq0 = (t0 + 16 * h) / TI;
     const bool bok = beam < e.B;
-    float* base = e.out + (size_t)beam * K * e.T2 * (size_t)e.C2 + e.g;
+    float* base = e.out + (size_t)beam * e.sb + (size_t)e.g * e.sc;
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         float s[4], v[4];
@@ -342,7 +343,7 @@ LBF_INLINE void stokes_store_ti(const floatx16 (&acc)[4], const EpiCtx& e, int b
         if (bok && tq < e.T2) {
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
-                float* p = base + ((size_t)kk * e.T2 + tq) * e.C2;
+                float* p = base + (size_t)kk * e.sk + (size_t)tq * e.st;
                 if (PLAIN) *p = v[kk];
                 else store_or_add(p, v[kk], e.first);
             }
@@ -474,7 +475,8 @@ LBF_INLINE void store_group_sums(float (&gs)[4], const EpiCtx& e, int beam, int 
     if (h != 0 || beam >= e.B || tq >= e.T2) return;
 #pragma unroll
     for (int kk = 0; kk < K; ++kk)
-        store_or_add(e.out + (((size_t)beam * K + kk) * e.T2 + tq) * (size_t)e.C2 + e.g, v[kk], e.first);
+        store_or_add(e.out + (size_t)beam * e.sb + (size_t)kk * e.sk + (size_t)tq * e.st + (size_t)e.g * e.sc, v[kk],
+                     e.first);
 }
 
 LBF_INLINE EpiCtx make_epi(const BlockDesc& d, int PR_, int g) {
@@ -489,6 +491,17 @@ LBF_INLINE EpiCtx make_epi(const BlockDesc& d, int PR_, int g) {
     e.g = g;
     e.c = 0;
     e.first = 1;
+    if (d.order == 0) {          // [B][K][T'][C']
+        e.sc = 1;
+        e.st = (size_t)e.C2;
+        e.sk = (size_t)e.T2 * e.C2;
+        e.sb = (size_t)e.K * e.T2 * e.C2;
+    } else {                     // [C'][K][T'][B]
+        e.sb = 1;
+        e.st = (size_t)d.B;
+        e.sk = (size_t)e.T2 * d.B;
+        e.sc = (size_t)e.K * e.T2 * d.B;
+    }
     return e;
 }
 

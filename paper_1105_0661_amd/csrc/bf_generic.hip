@@ -66,11 +66,12 @@ static hipError_t launch_fast(const BlockDesc& d, hipStream_t st) {
 }
 
 // lbf_beamform: the fast workers where they apply, the generic ones otherwise.
-// Fast Stokes blocks go through a beam-fastest staging buffer (stream-ordered
-// allocation) and a tiled transpose into the beam-major output.
+// The fast workers write Stokes products channel-major ([C'][K][T'][B], beams
+// fastest); a beam-major block (order 0) goes through a staging buffer of that
+// layout (stream-ordered allocation) and a tiled transpose.
 hipError_t launch_beamform(const BlockDesc& d, hipStream_t st) {
     if (!fast_path(d)) return launch_beamform_generic(d, st);
-    if (d.product == PR_VOLT) return launch_fast(d, st);
+    if (d.product == PR_VOLT || d.order == 1) return launch_fast(d, st);
     const int K = d.product == PR_IQUV ? 4 : 1;
     const int T2 = d.T / d.t_int;
     void* stage = nullptr;

@@ -29,6 +29,7 @@ struct BlockDesc {
     int S, C, T, B;
     int xtype, ctype, product;
     int t_int, f_int;
+    int order;          // Stokes: 0 = [B][K][T'][C'] (beam-major), 1 = [C'][K][T'][B] (channel-major)
 };
 
 // ---------------------------------------------------------------------------

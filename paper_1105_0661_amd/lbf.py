@@ -83,6 +83,9 @@ _PROTOS = {
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_beamform": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
+    "lbf_beamform_channel_major": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
+    "lbf_beam_major": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_beamform_batch": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.c_void_p]),
     "lbf_stokes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
@@ -179,9 +182,12 @@ def n_stokes(product: int) -> int:
     return {STOKES_I: 1, STOKES_IQUV: 4}[product]
 
 
-def output_shape(product: int, S: int, C: int, T: int, B: int, t_int: int = 1, f_int: int = 1):
+def output_shape(product: int, S: int, C: int, T: int, B: int, t_int: int = 1, f_int: int = 1,
+                 channel_major: bool = False):
     if product == VOLTAGES:
         return (C, B, T, 2, 2)
+    if channel_major:
+        return (C // f_int, n_stokes(product), T // t_int, B)
     return (B, n_stokes(product), T // t_int, C // f_int)
 
 
@@ -223,6 +229,29 @@ def beamform(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, strea
         out = torch.empty(output_shape(product, S, C, T, B, t_int, f_int), dtype=torch.float32, device=x.device)
     blk = make_block(x, w, product, t_int, f_int, out)
     _check(lib().lbf_beamform(ctypes.byref(blk), _stream(stream)))
+    return out
+
+
+def beamform_channel_major(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, stream=None):
+    """As ``beamform`` but Stokes stay channel-major: [C'][K][T'][B] f32."""
+    torch = _torch()
+    S, C, T = x.shape[0], x.shape[1], x.shape[2]
+    B = w.shape[1]
+    if out is None:
+        out = torch.empty(output_shape(product, S, C, T, B, t_int, f_int, channel_major=True), dtype=torch.float32,
+                          device=x.device)
+    blk = make_block(x, w, product, t_int, f_int, out)
+    _check(lib().lbf_beamform_channel_major(ctypes.byref(blk), _stream(stream)))
+    return out
+
+
+def beam_major(inp, out=None, stream=None):
+    """[C2][K][T2][B] f32 -> [B][K][T2][C2] (final order)."""
+    torch = _torch()
+    C2, K, T2, B = inp.shape
+    if out is None:
+        out = torch.empty((B, K, T2, C2), dtype=torch.float32, device=inp.device)
+    _check(lib().lbf_beam_major(_dev_ptr(inp, "inp"), C2, K, T2, B, _dev_ptr(out, "out"), _stream(stream)))
     return out
 
 
@@ -289,3 +318,91 @@ def block_footprint(S: int, C: int, T: int, B: int, xtype: int, ctype: int, prod
     out = BlockSizes()
     _check(lib().lbf_block_footprint(ctypes.byref(blk), ctypes.byref(out)))
     return out
+
+
+# --------------------------------------------------------------------------
+# streaming server
+# --------------------------------------------------------------------------
+
+class Server:
+    """lbf_server_* over a caller-owned device arena (a torch uint8 tensor).
+
+    ``submit`` copies the geometry; station samples (device tensor, or host
+    array / CPU tensor staged through the arena) and the output tensor are kept
+    referenced here until the ticket is released."""
+
+    def __init__(self, arena, max_inflight: int = 8, n_streams: int = 2, queue_capacity: int = 64,
+                 max_batch: int = 8, device: int = 0):
+        self.arena = arena
+        cfg = ServerCfg(d_arena=_dev_ptr(arena, "arena"), arena_bytes=arena.numel() * arena.element_size(),
+                        max_inflight=max_inflight, n_streams=n_streams, queue_capacity=queue_capacity,
+                        max_batch=max_batch, device=device)
+        h = ctypes.c_void_p()
+        _check(lib().lbf_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, obs_id: int, station_xyz, beam_dir, freq_hz, x, ctype: int, product: int, t_int: int = 1,
+               f_int: int = 1, out=None, ref_dir=None) -> int:
+        import numpy as np
+        torch = _torch()
+        pos = np.ascontiguousarray(station_xyz, dtype=np.float64)
+        dirs = np.ascontiguousarray(beam_dir, dtype=np.float64)
+        freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
+        ref = None if ref_dir is None else (ctypes.c_double * 3)(*[float(v) for v in ref_dir])
+        if isinstance(x, np.ndarray):
+            x = torch.from_numpy(np.ascontiguousarray(x))
+        on_host = not x.is_cuda
+        if not x.is_contiguous():
+            raise ValueError("x must be contiguous")
+        S, C, T = x.shape[:3]
+        B = dirs.shape[0]
+        if pos.shape != (S, 3) or dirs.shape != (B, 3) or freq.shape != (C,):
+            raise ValueError("geometry shapes %s %s %s do not match samples [S=%d][C=%d]"
+                             % (pos.shape, dirs.shape, freq.shape, S, C))
+        if out is None:
+            out = torch.empty(output_shape(product, S, C, T, B, t_int, f_int), dtype=torch.float32,
+                              device=self.arena.device)
+        job = Job(obs_id=obs_id, station_xyz=pos.ctypes.data, S=S, beam_dir=dirs.ctypes.data, B=B,
+                  ref_dir=ctypes.addressof(ref) if ref is not None else None,
+                  freq_hz=freq.ctypes.data, C=C, x=x.data_ptr(), xtype=xtype_of(x), T=T, x_on_host=int(on_host),
+                  ctype=ctype, product=product, t_int=t_int, f_int=f_int, d_out=_dev_ptr(out, "out"))
+        t = ctypes.c_uint64()
+        _check(lib().lbf_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)))
+        self._keep[t.value] = (x, out)
+        return t.value
+
+    def output(self, ticket: int):
+        return self._keep[ticket][1]
+
+    def poll(self, ticket: int) -> JobStatus:
+        st = JobStatus()
+        _check(lib().lbf_server_poll(self._h, ticket, ctypes.byref(st)))
+        return st
+
+    def wait(self, ticket: int, timeout_ms: int = 60000) -> JobStatus:
+        st = JobStatus()
+        _check(lib().lbf_server_wait(self._h, ticket, timeout_ms, ctypes.byref(st)))
+        return st
+
+    def release(self, ticket: int):
+        _check(lib().lbf_server_release(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def close(self):
+        if self._h:
+            _check(lib().lbf_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -201,6 +201,43 @@ def test_transpose_is_exact():
     assert torch.equal(ov, v.permute(1, 3, 2, 0, 4).contiguous())
 
 
+@pytest.mark.parametrize("ctype,S,product,t_int,f_int", [
+    (lbf.F32, 11, lbf.STOKES_IQUV, 16, 1),      # fast FP32 worker
+    (lbf.F16, 33, lbf.STOKES_I, 4, 1),          # fast FP16 worker
+    (lbf.BF16, 11, lbf.STOKES_IQUV, 8, 1),      # fast BF16 worker
+    (lbf.F16, 70, lbf.STOKES_IQUV, 16, 1),      # generic worker (> 64 stations)
+    (lbf.F32, 11, lbf.STOKES_IQUV, 2, 2),       # generic worker (channel integration)
+    (lbf.BF16, 9, lbf.STOKES_I, 64, 1),         # generic worker (t_int >= 32)
+], ids=["f32-fast", "f16-fast", "bf16-fast", "f16-S70", "f32-fint2", "bf16-tint64"])
+def test_channel_major_then_beam_major_equals_fused(ctype, S, product, t_int, f_int):
+    torch = _torch()
+    xtype = "ci8" if ctype != lbf.F32 else "ci16"
+    blk = synth.make_block(S, 75, 2, 4, 128, xtype, 16.0 if xtype == "ci8" else 40.0, tag=(1105, 661, 65))
+    flush("channel-major %s S=%d K=%d t_int=%d f_int=%d" % (CT_NAMES[ctype], S, product, t_int, f_int))
+    x, w = to_dev(blk.x), _weights(blk, ctype)
+    cm = lbf.beamform_channel_major(x, w, product, t_int, f_int)      # [C'][K][T'][B]
+    bm = lbf.beam_major(cm)
+    fused = lbf.beamform(x, w, product, t_int, f_int)
+    torch.cuda.synchronize()
+    assert cm.shape == (blk.C // f_int, product, blk.T // t_int, blk.B)
+    assert torch.equal(bm, fused)
+    _check_stokes(bm.cpu().numpy(), _oracle_stokes(blk, product, t_int, f_int), TOL[ctype], "channel-major")
+
+
+def test_beam_major_reorder_is_exact():
+    torch = _torch()
+    g = torch.Generator(device="cuda:0").manual_seed(4)
+    for shape in [(37, 4, 9, 70), (1, 1, 1, 1), (65, 1, 3, 129), (3, 4, 300, 5)]:
+        a = torch.randn(shape, device="cuda:0", generator=g)
+        o = lbf.beam_major(a)
+        torch.cuda.synchronize()
+        assert torch.equal(o, a.permute(3, 1, 2, 0).contiguous()), shape
+    a = torch.randn((4, 4, 4, 4), device="cuda:0", generator=g)
+    with pytest.raises(lbf.LbfError) as ei:
+        lbf.beam_major(a, out=a)
+    assert ei.value.code == lbf.E_INVAL
+
+
 def test_voltages_beam_major_order_matches_oracle():
     torch = _torch()
     blk = synth.make_block(6, 33, 1, 3, 40, "ci8", 10.0, tag=(1105, 661, 57))

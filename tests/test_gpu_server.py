@@ -1,0 +1,161 @@
+"""GPU tests of the streaming server (lbf_server_*): continuous batching of
+blocks of different shapes, each result the same alone and in the mix, host
+staging, admission by arena footprint with weight-cache eviction, and the
+status codes of the queue."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1105_0661_amd import lbf, synth
+from tests._util import flush, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {lbf.F32: 1e-5, lbf.F16: 3e-3, lbf.BF16: 3e-3}
+CT_NAMES = {lbf.F32: "f32", lbf.F16: "f16", lbf.BF16: "bf16"}
+
+# (S, B, nsb, nch, T, xtype, product, t_int, f_int, obs_id)
+MIX = [
+    (24, 17, 2, 16, 64, "ci8", lbf.STOKES_I, 16, 1, 1),
+    (40, 150, 1, 16, 96, "ci16", lbf.STOKES_IQUV, 16, 1, 2),
+    (64, 33, 3, 8, 32, "ci8", lbf.STOKES_IQUV, 32, 1, 3),
+    (31, 1, 1, 5, 48, "ci16", lbf.STOKES_I, 4, 1, 4),
+    (70, 90, 1, 4, 64, "ci8", lbf.STOKES_IQUV, 16, 2, 5),     # > 64 stations, channel integration
+    (24, 17, 2, 16, 64, "ci8", lbf.STOKES_I, 16, 1, 1),       # same observation as the first: cached weights
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _blocks():
+    out = []
+    for i, (S, B, nsb, nch, T, xt, prod, ti, fi, obs) in enumerate(MIX):
+        blk = synth.make_block(S, B, nsb, nch, T, xt, 16.0 if xt == "ci8" else 40.0, tag=(1105, 661, 70 + obs))
+        out.append((blk, prod, ti, fi, obs))
+    return out
+
+
+def _arena(nbytes):
+    torch = _torch()
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+
+
+def _submit(srv, blk, prod, ti, fi, obs, ctype, x):
+    return srv.submit(obs, blk.station_xyz, blk.beam_dir, blk.freq_hz, x, ctype, prod, ti, fi, ref_dir=blk.ref_dir)
+
+
+@pytest.mark.parametrize("ctype", [lbf.F16, lbf.BF16, lbf.F32], ids=["f16", "bf16", "f32"])
+def test_results_alone_equal_results_in_the_mix(ctype):
+    torch = _torch()
+    blocks = _blocks()
+    xs = [to_dev(b[0].x) for b in blocks]
+    # alone: one job on the device at a time
+    alone = []
+    with lbf.Server(_arena(256 << 20), max_inflight=1, n_streams=1, max_batch=1) as srv:
+        for (blk, prod, ti, fi, obs), x in zip(blocks, xs):
+            flush("server alone %s S=%d B=%d" % (CT_NAMES[ctype], blk.S, blk.B))
+            t = _submit(srv, blk, prod, ti, fi, obs, ctype, x)
+            st = srv.wait(t)
+            assert st.state == lbf.JOB_DONE and st.batch_size == 1, (st.state, st.error)
+            alone.append(srv.output(t).clone())
+            srv.release(t)
+    # mix: all submitted at once, fused into shared launches on two streams
+    flush("server mix %s" % CT_NAMES[ctype])
+    with lbf.Server(_arena(256 << 20), max_inflight=16, n_streams=2, max_batch=8) as srv:
+        tickets = [_submit(srv, blk, prod, ti, fi, obs, ctype, x) for (blk, prod, ti, fi, obs), x in zip(blocks, xs)]
+        sts = [srv.wait(t) for t in tickets]
+        assert all(s.state == lbf.JOB_DONE for s in sts), [(s.state, s.error) for s in sts]
+        mixed = [srv.output(t).clone() for t in tickets]
+        if ctype != lbf.F32:
+            assert max(s.batch_size for s in sts) > 1      # admitted together, one persistent launch
+        for s in sts:
+            assert s.t_submit_ns <= s.t_admit_ns <= s.t_start_ns <= s.t_done_ns
+    torch.cuda.synchronize()
+    for i, ((blk, prod, ti, fi, obs), a, m) in enumerate(zip(blocks, alone, mixed)):
+        assert torch.equal(a, m), "job %d differs alone vs mix" % i
+        direct = lbf.beamform(xs[i], lbf.compute_weights(to_dev(blk.station_xyz), to_dev(blk.beam_dir),
+                                                         to_dev(blk.freq_hz), ctype, ref_dir=blk.ref_dir),
+                              prod, ti, fi)
+        torch.cuda.synchronize()
+        assert torch.equal(a, direct), "job %d differs from lbf_beamform" % i
+        ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, ti, fi, 8)
+        got = a.cpu().numpy()
+        for k in range(ref.shape[1]):
+            assert relerr(got[:, k], ref[:, k]) <= TOL[ctype], (i, k)
+
+
+def test_host_staged_input_equals_device_input():
+    torch = _torch()
+    blk, prod, ti, fi, obs = _blocks()[1]
+    with lbf.Server(_arena(64 << 20), max_inflight=2, n_streams=2, max_batch=2) as srv:
+        t_dev = _submit(srv, blk, prod, ti, fi, obs, lbf.F16, to_dev(blk.x))
+        t_host = _submit(srv, blk, prod, ti, fi, obs, lbf.F16, blk.x)          # host array, staged in the arena
+        a, b = srv.wait(t_dev), srv.wait(t_host)
+        assert a.state == lbf.JOB_DONE and b.state == lbf.JOB_DONE
+        assert torch.equal(srv.output(t_dev), srv.output(t_host))
+
+
+def _align(v):
+    return (v + 255) // 256 * 256
+
+
+def test_admission_by_footprint_evicts_idle_weights():
+    # an arena that holds one observation's weights at a time: jobs of
+    # alternating observations still all complete, with the right results
+    torch = _torch()
+    blocks = _blocks()[:2]
+    xs = [to_dev(b[0].x) for b in blocks]
+    need = max(_align(b.C * b.B * b.S * 4) + _align(8 * (3 * b.S + 3 * b.B + b.C)) for b, *_ in blocks)
+    with lbf.Server(_arena(need + 256), max_inflight=4, n_streams=2, max_batch=4) as srv:
+        order = [0, 1, 0, 1, 1, 0]
+        tickets = [_submit(srv, *blocks[i], lbf.F16, xs[i]) for i in order]
+        outs = []
+        for t in tickets:
+            st = srv.wait(t)
+            assert st.state == lbf.JOB_DONE, (st.state, st.error)
+            outs.append(srv.output(t).clone())
+    torch.cuda.synchronize()
+    for i in range(2):
+        blk, prod, ti, fi, obs = blocks[i]
+        ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, ti, fi, 8)
+        first = outs[order.index(i)]
+        assert relerr(first.cpu().numpy(), ref) <= TOL[lbf.F16]
+        for j, o in zip(order, outs):
+            if j == i:
+                assert torch.equal(o, first)
+
+
+def test_queue_status_codes():
+    blk, prod, ti, fi, obs = _blocks()[1]
+    x = to_dev(blk.x)
+    # footprint beyond the arena: refused at submit
+    with lbf.Server(_arena(4096), max_inflight=1, n_streams=1) as srv:
+        with pytest.raises(lbf.LbfError) as ei:
+            _submit(srv, blk, prod, ti, fi, obs, lbf.F16, x)
+        assert ei.value.code == lbf.E_NOMEM
+    # a bounded queue refuses work rather than growing: one job on the device,
+    # one queued, blocks that take a fraction of a millisecond each
+    big = synth.make_block(64, 300, 8, 64, 768, "ci8", 16.0, tag=(1105, 661, 79))
+    xb = to_dev(big.x)
+    with lbf.Server(_arena(64 << 20), max_inflight=1, n_streams=1, queue_capacity=1, max_batch=1) as srv:
+        codes, tickets = [], []
+        flush("server queue bound")
+        for _ in range(32):
+            try:
+                tickets.append(_submit(srv, big, lbf.STOKES_IQUV, 16, 1, 7, lbf.F16, xb))
+            except lbf.LbfError as e:
+                codes.append(e.code)
+        assert lbf.E_BUSY in codes
+        assert set(codes) == {lbf.E_BUSY}
+        for t in tickets:
+            assert srv.wait(t).state == lbf.JOB_DONE
+        with pytest.raises(lbf.LbfError) as ei:
+            srv.poll(10 ** 9)
+        assert ei.value.code == lbf.E_NOTFOUND
+        srv.release(tickets[0])
+        with pytest.raises(lbf.LbfError) as ei:
+            srv.poll(tickets[0])
+        assert ei.value.code == lbf.E_NOTFOUND
