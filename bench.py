@@ -44,6 +44,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--profile-precision", action="store_true",
                    help="profiling run: time only the 488-beam block paths (no JSON line)")
+    p.add_argument("--serve-seconds", type=float, default=8.0, help="measured seconds of the streaming run")
     p.add_argument("--copy-calibration", action="store_true",
                    help="counter calibration run: three plain 1 GiB device-to-device copies (no JSON line)")
     return p.parse_args()
@@ -95,6 +96,157 @@ def time_path(lbf, torch, x, geo, ctype, product, t_int, f_int, steps, warmup):
 
     return dict(wall_s=wall, step_ms=span(0, 3), weights_ms=span(0, 1), beamform_ms=span(1, 2),
                 reorder_ms=span(2, 3), out=out, w=w)
+
+
+def t_roof_s(fp):
+    """Roofline time of one FP16-MFMA block: max(MFMA, HBM) at the datasheet peaks."""
+    return max(fp.flops / (PEAK["f16_TFLOPs"] * 1e12),
+               (fp.input_bytes + fp.weight_bytes + fp.output_bytes) / (PEAK["hbm_GBps"] * 1e9))
+
+
+def make_jobs(lbf, torch, synth, dev, log_every=4):
+    """The uneven batch: 12 one-second blocks of random shape, resident in HBM,
+    with their FP16 weights."""
+    jobs = []
+    for i, js in enumerate(synth.config3_jobs()):
+        blk = synth.block_for_job(js, threads=16)
+        x = torch.from_numpy(blk.x).to(dev)
+        del blk.x
+        geo = (torch.from_numpy(blk.station_xyz).to(dev), torch.from_numpy(blk.beam_dir).to(dev),
+               torch.from_numpy(blk.freq_hz).to(dev), blk.ref_dir)
+        prod = lbf.STOKES_I if js.product == "I" else lbf.STOKES_IQUV
+        w = lbf.compute_weights(*geo[:3], lbf.F16, ref_dir=geo[3])
+        jobs.append(dict(spec=js, blk=blk, x=x, w=w, prod=prod, geo=geo))
+        if (i + 1) % log_every == 0:
+            log("generated %d uneven-batch jobs" % (i + 1))
+    return jobs
+
+
+def batched(lbf, torch, jobs, steps, warmup):
+    """One persistent launch over all jobs (lbf_beamform_batch) against one
+    lbf_beamform per job, FP16 MFMA, weights resident."""
+    items, bs, froof, fl = [], 0.0, 0.0, 0.0
+    for j in jobs:
+        js = j["spec"]
+        out = torch.empty(lbf.output_shape(j["prod"], js.S, j["x"].shape[1], js.T, js.B, 16, 1), dtype=torch.float32,
+                          device=j["x"].device)
+        items.append((j["x"], j["w"], j["prod"], 16, 1, out))
+        fp = lbf.block_footprint(js.S, j["x"].shape[1], js.T, js.B, lbf.CI8 if js.xtype == "ci8" else lbf.CI16,
+                                 lbf.F16, j["prod"], 16, 1)
+        bs += float(js.B) * j["x"].shape[1] * js.T
+        froof += t_roof_s(fp)
+        fl += fp.flops
+
+    def run(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_batch = run(lambda: lbf.beamform_batch(items))
+    ms_seq = run(lambda: [lbf.beamform(*it[:5], out=it[5]) for it in items])
+    return {"workload": "12 concurrent one-second observations: stations U{24..64}, beams U{1..400}, "
+                        "16/64/256 channels x U{8..64} subbands, ci8/ci16, Stokes I or IQUV x16, FP16 MFMA, "
+                        "one persistent launch",
+            "jobs": [{"S": j["spec"].S, "B": j["spec"].B, "C": int(j["x"].shape[1]), "T": j["spec"].T,
+                      "xtype": j["spec"].xtype, "product": j["spec"].product} for j in jobs],
+            "ms_per_batch": ms_batch, "ms_sequential": ms_seq,
+            "beam_samples_per_s": bs / (ms_batch / 1e3), "TFLOPs": fl / (ms_batch / 1e3) / 1e12,
+            "roofline_ms": froof * 1e3, "roofline_frac": froof * 1e3 / ms_batch,
+            "batch_vs_sequential": ms_seq / ms_batch}
+
+
+def serving(lbf, torch, synth, jobs, blk1, x1, blk2, x2, seconds, warm_s):
+    """Streaming request loop: Poisson arrivals of 0.25/0.5/1 s blocks of 16
+    fixed observations (shapes of the one-second block, the precision block and
+    the uneven batch), offered at the full array's 198.4 Gb/s, through the
+    lbf_server (footprint admission, device weight cache, persistent batches
+    on a stream pool), FP16 MFMA.  Then a closed loop for the sustainable rate."""
+    dev = x1.device
+    rng = np.random.default_rng([1105, 661, 4])
+    base = [(blk1, x1, lbf.STOKES_IQUV), (blk2, x2, lbf.STOKES_IQUV)]
+    base += [(j["blk"], j["x"], j["prod"]) for j in jobs]
+    obs = []
+    for i in range(16):
+        blk, x, prod = base[i % len(base)]
+        d = float(rng.choice([0.25, 0.5, 1.0]))
+        T = synth.samples_per_block(d, blk.nch)
+        T = min(T, x.shape[2]) // 16 * 16
+        xs = x[:, :, :T].contiguous() if T < x.shape[2] else x
+        outs = [torch.empty(lbf.output_shape(prod, blk.S, blk.C, T, blk.B, 16, 1), dtype=torch.float32, device=dev)
+                for _ in range(3)]
+        obs.append(dict(blk=blk, x=xs, prod=prod, T=T, outs=outs, seconds=d, nbytes=xs.numel() * xs.element_size(),
+                        next=0))
+    mean_bytes = float(np.mean([o["nbytes"] for o in obs]))
+    rate_bps = 198.4e9 / 8
+    lam = rate_bps / mean_bytes
+    arena = torch.empty(24 << 30, dtype=torch.uint8, device=dev)
+
+    def submit(srv, o):
+        out = o["outs"][o["next"] % 3]
+        o["next"] += 1
+        b = o["blk"]
+        return srv.submit(id(o) & 0xffffffff, b.station_xyz, b.beam_dir, b.freq_hz, o["x"], lbf.F16, o["prod"], 16, 1,
+                          out=out, ref_dir=b.ref_dir)
+
+    res = {}
+    with lbf.Server(arena, max_inflight=8, n_streams=2, queue_capacity=256, max_batch=8) as srv:
+        # open loop at the real-time rate
+        arrivals = synth.poisson_arrivals(lam, warm_s + seconds, seed_tag=(1105, 661, 4))
+        pick = rng.integers(0, len(obs), size=len(arrivals))
+        t0 = time.monotonic_ns()
+        pending = []
+        for a, k in zip(arrivals, pick):
+            due = t0 + int(a * 1e9)
+            while time.monotonic_ns() < due:
+                pass
+            pending.append((due, a, obs[k], submit(srv, obs[k])))
+        lat, bits, first_due, last_due, done_last = [], 0.0, None, 0, 0
+        for due, a, o, t in pending:
+            st = srv.wait(t, 60000)
+            if st.state != lbf.JOB_DONE:
+                raise RuntimeError("serving job failed: state %d error %d" % (st.state, st.error))
+            if a >= warm_s:
+                lat.append((st.t_done_ns - due) / 1e6)
+                bits += o["nbytes"] * 8
+                first_due = due if first_due is None else first_due
+                last_due = due
+                done_last = max(done_last, st.t_done_ns)
+            srv.release(t)
+        offered_s = (last_due - first_due) / 1e9          # arrival span of the measured blocks
+        served_s = (done_last - first_due) / 1e9          # first arrival to last completion
+        res["open_loop"] = {"offered_Gbps_nominal": 198.4, "arrival_rate_hz": lam, "blocks": len(lat),
+                            "offered_Gbps": bits / offered_s / 1e9, "completed_Gbps": bits / served_s / 1e9,
+                            "sustain_ratio": offered_s / served_s,
+                            "p50_block_latency_ms": float(np.percentile(lat, 50)),
+                            "p99_block_latency_ms": float(np.percentile(lat, 99))}
+        # closed loop: keep the queue full
+        n = 96
+        order = rng.integers(0, len(obs), size=n)
+        t1 = time.monotonic_ns()
+        tickets = [(obs[k], submit(srv, obs[k])) for k in order]
+        lat2, bits2, last = [], 0.0, t1
+        for o, t in tickets:
+            st = srv.wait(t, 60000)
+            if st.state != lbf.JOB_DONE:
+                raise RuntimeError("serving job failed: state %d error %d" % (st.state, st.error))
+            lat2.append((st.t_done_ns - st.t_submit_ns) / 1e6)
+            bits2 += o["nbytes"] * 8
+            last = max(last, st.t_done_ns)
+            srv.release(t)
+        res["closed_loop"] = {"blocks": n, "sustainable_Gbps": bits2 / ((last - t1) / 1e9) / 1e9,
+                              "realtime_factor": bits2 / ((last - t1) / 1e9) / 198.4e9}
+    res["workload"] = ("Poisson arrivals of 0.25/0.5/1 s blocks of 16 observations (one-second-block, precision-block "
+                       "and uneven-batch shapes), offered at 198.4 Gb/s of station input, device-resident input, "
+                       "lbf_server with weight cache, FP16 MFMA")
+    res["mean_block_GB"] = mean_bytes / 1e9
+    return res
 
 
 KERNEL_SOURCES = ["lbf_device.h", "bf_common.h", "bf_workers.h", "bf_fast_impl.h", "bf_fast_f32.hip"]
@@ -220,9 +372,8 @@ def main():
 
     # ---------------- the 488-beam precision block (MFMA-bound) ----------------
     extra = None
+    batch_res = serve_res = None
     if not a.no_extra and not only:
-        del x
-        torch.cuda.empty_cache()
         b2 = synth.config2(threads=16)
         x2 = torch.from_numpy(b2.x).to(dev)
         geo2 = (torch.from_numpy(b2.station_xyz).to(dev), torch.from_numpy(b2.beam_dir).to(dev),
@@ -240,7 +391,18 @@ def main():
                            "mfma_TFLOPs": fp2.flops / (kms / 1e3) / 1e12,
                            "mfma_frac": fp2.flops / (kms / 1e3) / 1e12 / PEAK["f16_TFLOPs"]}
             log("precision %s: %s" % (name, extra[name]))
-        del x2
+        del b2.x
+
+        # ---------------- uneven batch and streaming service ----------------
+        jobs = make_jobs(lbf, torch, synth, dev)
+        batch_res = batched(lbf, torch, jobs, max(3, a.steps // 4), 1)
+        log("batched: %.3f ms per batch, %.3g beam-samples/s, %.2f of roofline, %.2fx sequential"
+            % (batch_res["ms_per_batch"], batch_res["beam_samples_per_s"], batch_res["roofline_frac"],
+               batch_res["batch_vs_sequential"]))
+        serve_res = serving(lbf, torch, synth, jobs, blk, x, b2, x2, a.serve_seconds, 2.0)
+        log("serving: %s" % serve_res["open_loop"])
+        log("serving closed loop: %s" % serve_res["closed_loop"])
+        del jobs, x2
 
     # ---------------- the JSON line ----------------
     main_name = "f32" if "f32" in res else sorted(res)[0]
@@ -300,6 +462,10 @@ def main():
         line["fp16_mfma_vs_fp32_speedup"] = paths["f16"]["beam_samples_per_s"] / paths["f32"]["beam_samples_per_s"]
     if extra:
         line["precision_block"] = extra
+    if batch_res:
+        line["batched"] = batch_res
+    if serve_res:
+        line["serving"] = serve_res
     line["context"] = "paper: 198 Gb/s station input sustained on one Blue Gene/P rack (Sections 1, 5)"
     print(json.dumps(line), flush=True)
 

@@ -2,7 +2,10 @@
 // blocks (Section 7 of Mol & Romein: independent observations processed in
 // parallel while resources allow).  Work groups pull items from a device
 // counter; each item runs exactly the worker lbf_beamform would run for it,
-// so every block's result is bitwise the same alone or in a batch.
+// so every block's result is bitwise the same alone or in a batch.  Blocks
+// outside the fast path (more than 64 stations, t_int other than 16, channel
+// integration, complex float input) are rare in a batch and run through their
+// own launches on the same stream.
 #include "bf_common.h"
 #include "bf_workers.h"
 
@@ -19,26 +22,20 @@ struct BatchArgs {
 // workers; everything else in a batch runs the generic ones.
 __host__ __device__ inline bool batch_fast(const BlockDesc& d) { return fast_path(d) && d.t_int == 16; }
 
-template <int CT, int PR>
-LBF_INLINE void batch_item(const BlockDesc& d, int item, int nbg, uint32_t* wh) {
-    if (batch_fast(d)) {
-        if (d.xtype == XT_CI8) {
-            if (d.S <= 32) item_h_fast<XT_CI8, CT, PR, 16, 4>(d, item, nbg, wh);
-            else item_h_fast<XT_CI8, CT, PR, 16, 8>(d, item, nbg, wh);
-        } else {
-            if (d.S <= 32) item_h_fast<XT_CI16, CT, PR, 16, 4>(d, item, nbg, wh);
-            else item_h_fast<XT_CI16, CT, PR, 16, 8>(d, item, nbg, wh);
-        }
+template <int XT, int CT, int PR>
+LBF_INLINE void batch_item_fast(const BlockDesc& d, int item, int nbg, uint32_t* at) {
+    if (fast_h_streams(d) == 1) {
+        if (d.S <= 32) item_h_fast<XT, CT, PR, 16, 4, 1>(d, item, nbg, at);
+        else item_h_fast<XT, CT, PR, 16, 8, 1>(d, item, nbg, at);
     } else {
-        if (d.xtype == XT_CI8) item_h_generic<XT_CI8, CT, PR>(d, item, nbg, wh);
-        else if (d.xtype == XT_CI16) item_h_generic<XT_CI16, CT, PR>(d, item, nbg, wh);
-        else item_h_generic<XT_CF32, CT, PR>(d, item, nbg, wh);
+        if (d.S <= 32) item_h_fast<XT, CT, PR, 16, 4, 2>(d, item, nbg, at);
+        else item_h_fast<XT, CT, PR, 16, 8, 2>(d, item, nbg, at);
     }
 }
 
 template <int CT>
-__global__ __launch_bounds__(kThreads) void bf_batch_kernel(BatchArgs a, int* counter) {
-    __shared__ __attribute__((aligned(16))) uint32_t wh[kWhWords];
+__global__ __launch_bounds__(kThreadsH) void bf_batch_kernel(BatchArgs a, int* counter) {
+    __shared__ __attribute__((aligned(16))) uint32_t at[2 * 2 * kATileWords];
     __shared__ int next;
     const int total = a.item_start[a.n];
     for (;;) {
@@ -50,8 +47,14 @@ __global__ __launch_bounds__(kThreads) void bf_batch_kernel(BatchArgs a, int* co
         int j = 0;
         while (j + 1 < a.n && a.item_start[j + 1] <= it) ++j;
         const BlockDesc& d = a.blk[j];
-        if (d.product == PR_I) batch_item<CT, PR_I>(d, it - a.item_start[j], a.nbg[j], wh);
-        else batch_item<CT, PR_IQUV>(d, it - a.item_start[j], a.nbg[j], wh);
+        const int item = it - a.item_start[j];
+        if (d.xtype == XT_CI8) {
+            if (d.product == PR_I) batch_item_fast<XT_CI8, CT, PR_I>(d, item, a.nbg[j], at);
+            else batch_item_fast<XT_CI8, CT, PR_IQUV>(d, item, a.nbg[j], at);
+        } else {
+            if (d.product == PR_I) batch_item_fast<XT_CI16, CT, PR_I>(d, item, a.nbg[j], at);
+            else batch_item_fast<XT_CI16, CT, PR_IQUV>(d, item, a.nbg[j], at);
+        }
     }
 }
 
@@ -61,66 +64,69 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
 }
 
 hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, hipStream_t st) {
+    // blocks outside the batch kernel's path: their own launches
     BatchArgs a;
-    a.n = n;
+    a.n = 0;
     a.item_start[0] = 0;
-    // fast Stokes blocks stage beam-fastest and are transposed afterwards
     size_t stage_bytes = 0, stage_off[kMaxBatch];
+    int src[kMaxBatch];
     for (int j = 0; j < n; ++j) {
-        stage_off[j] = stage_bytes;
-        if (batch_fast(blks[j])) {
-            const int K = blks[j].product == PR_IQUV ? 4 : 1;
-            stage_bytes += ((size_t)blks[j].C * K * (blks[j].T / blks[j].t_int) * blks[j].B * sizeof(float) + 255) & ~(size_t)255;
+        if (!batch_fast(blks[j])) {
+            const hipError_t e = launch_beamform(blks[j], st);
+            if (e != hipSuccess) return e;
+            continue;
         }
+        const int K = blks[j].product == PR_IQUV ? 4 : 1;
+        stage_off[a.n] = stage_bytes;
+        stage_bytes += ((size_t)blks[j].C * K * (blks[j].T / blks[j].t_int) * blks[j].B * sizeof(float) + 255) &
+                       ~(size_t)255;
+        src[a.n] = j;
+        a.blk[a.n] = blks[j];
+        a.n++;
     }
+    if (a.n == 0) return hipSuccess;
+    // Stokes go to channel-major staging first (as in lbf_beamform), then to
+    // the beam-major outputs
     char* stage = nullptr;
-    if (stage_bytes) {
-        hipError_t e = hipMallocAsync((void**)&stage, stage_bytes, st);
-        if (e != hipSuccess) return e;
-    }
-    for (int j = 0; j < n; ++j) {
-        a.blk[j] = blks[j];
-        if (batch_fast(blks[j])) a.blk[j].out = stage + stage_off[j];
+    hipError_t e = hipMallocAsync((void**)&stage, stage_bytes, st);
+    if (e != hipSuccess) return e;
+    for (int j = 0; j < a.n; ++j) {
+        a.blk[j].out = stage + stage_off[j];
+        a.blk[j].order = 1;
         int nbg;
-        const int items = batch_fast(blks[j]) ? block_items_fast_h(blks[j], &nbg) : block_items(blks[j], &nbg);
+        const int items = block_items_fast_h(a.blk[j], &nbg);
         a.nbg[j] = nbg;
         a.item_start[j + 1] = a.item_start[j] + items;
     }
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, st, d_counter, 1, 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        if (stage) (void)hipFreeAsync(stage, st);
-        return e;
-    }
-    // one resident work group per slot the hardware offers: the queue, not the
-    // grid, spreads the uneven items
-    int dev = 0, cus = 256, per_cu = 1;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (blks[0].ctype == CT_F16)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bf_batch_kernel<CT_F16>, kThreads, 0);
-    else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bf_batch_kernel<CT_BF16>, kThreads, 0);
-    if (per_cu < 1) per_cu = 1;
-    const int total = a.item_start[n];
-    const int slots = cus * per_cu;
-    const int grid = total < slots ? total : slots;
-    if (blks[0].ctype == CT_F16)
-        hipLaunchKernelGGL(bf_batch_kernel<CT_F16>, dim3(grid), dim3(kThreads), 0, st, a, d_counter);
-    else
-        hipLaunchKernelGGL(bf_batch_kernel<CT_BF16>, dim3(grid), dim3(kThreads), 0, st, a, d_counter);
     e = hipGetLastError();
-    for (int j = 0; j < n && e == hipSuccess; ++j) {
-        if (!batch_fast(blks[j])) continue;
-        const BlockDesc& b = blks[j];
+    if (e == hipSuccess) {
+        // one resident work group per slot the hardware offers: the queue, not
+        // the grid, spreads the uneven items
+        int dev = 0, cus = 256, per_cu = 1;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (a.blk[0].ctype == CT_F16)
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bf_batch_kernel<CT_F16>, kThreadsH, 0);
+        else
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bf_batch_kernel<CT_BF16>, kThreadsH, 0);
+        if (per_cu < 1) per_cu = 1;
+        const int total = a.item_start[a.n];
+        const int slots = cus * per_cu;
+        const int grid = total < slots ? total : slots;
+        if (a.blk[0].ctype == CT_F16)
+            hipLaunchKernelGGL(bf_batch_kernel<CT_F16>, dim3(grid), dim3(kThreadsH), 0, st, a, d_counter);
+        else
+            hipLaunchKernelGGL(bf_batch_kernel<CT_BF16>, dim3(grid), dim3(kThreadsH), 0, st, a, d_counter);
+        e = hipGetLastError();
+    }
+    for (int j = 0; j < a.n && e == hipSuccess; ++j) {
+        const BlockDesc& b = blks[src[j]];
         const int K = b.product == PR_IQUV ? 4 : 1;
         e = launch_stage_to_beam_major((const float*)(stage + stage_off[j]), b.C, K * (b.T / b.t_int), b.B,
                                        (float*)b.out, st);
     }
-    if (stage) {
-        const hipError_t ef = hipFreeAsync(stage, st);
-        if (e == hipSuccess) e = ef;
-    }
-    return e;
+    const hipError_t ef = hipFreeAsync(stage, st);
+    return e != hipSuccess ? e : ef;
 }
 
 }  // namespace lbf

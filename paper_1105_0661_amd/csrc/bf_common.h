@@ -24,8 +24,6 @@ constexpr int kStationChunk = 64;               // stations whose weights sit in
 constexpr int kWavesPerGroup = 4;
 constexpr int kThreads = kWave * kWavesPerGroup;
 constexpr int kWRow = kStationChunk + 4;        // LDS row of packed f16/bf16 weights (words)
-constexpr int kSuperGroup = 4 * kBeamGroup;     // beams of one fast FP16/BF16 work item
-constexpr int kWhWords = kSuperGroup * kWRow;   // their LDS weights: 136 KB
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
@@ -190,6 +188,47 @@ template <> struct Conv<XT_CF32, CT_F16> {
     }
 };
 
+// Plain 16-bit operand words of one station sample: fx = (x_re, x_im),
+// fy = (y_re, y_im) -- the fast workers put the re/im mixing of the complex
+// product into two weight variants instead.
+template <int XT, int CT> struct Conv2;
+
+// complex int8 -> f16, exact: the byte-bias trick of Conv<XT_CI8, CT_F16>
+template <> struct Conv2<XT_CI8, CT_F16> {
+    LBF_INLINE static void xy(int v, uint32_t& fx, uint32_t& fy) {
+        const uint32_t u = (uint32_t)v ^ 0x80808080u;
+        halfx2 hx = __builtin_bit_cast(halfx2, __builtin_amdgcn_perm(u, 0x64646464u, 0x00050004u));
+        halfx2 hy = __builtin_bit_cast(halfx2, __builtin_amdgcn_perm(u, 0x64646464u, 0x00070006u));
+        const halfx2 bias = {(_Float16)-1152.0f, (_Float16)-1152.0f};
+        fx = __builtin_bit_cast(uint32_t, hx + bias);
+        fy = __builtin_bit_cast(uint32_t, hy + bias);
+    }
+};
+
+// complex int16 -> f16 (exact for |x| <= 2048, round-to-nearest-even beyond)
+template <> struct Conv2<XT_CI16, CT_F16> {
+    LBF_INLINE static void xy(shortx4 v, uint32_t& fx, uint32_t& fy) {
+        const halfx2 hx = {(_Float16)v[0], (_Float16)v[1]};
+        const halfx2 hy = {(_Float16)v[2], (_Float16)v[3]};
+        fx = __builtin_bit_cast(uint32_t, hx);
+        fy = __builtin_bit_cast(uint32_t, hy);
+    }
+};
+
+// -> bf16: int8 exactly (float bits truncated), int16 round-to-nearest-even
+template <int XT> struct Conv2<XT, CT_BF16> {
+    LBF_INLINE static void xy(typename Raw<XT>::type v, uint32_t& fx, uint32_t& fy) {
+        const floatx4 f = Raw<XT>::cvt(v);
+        if (XT == XT_CI8) {
+            fx = pack_bf16_exact(f[0], f[1]);
+            fy = pack_bf16_exact(f[2], f[3]);
+        } else {
+            fx = pack_bf16(f[0], f[1]);
+            fy = pack_bf16(f[2], f[3]);
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // weight staging into LDS
 // ---------------------------------------------------------------------------
@@ -198,7 +237,7 @@ template <> struct Conv<XT_CF32, CT_F16> {
 // [b0, b0+128) of channel c; zero outside [0,S) x [0,B).
 LBF_INLINE void stage_weights_f32(float* wl, const BlockDesc& d, int c, int b0, int s0) {
     const float2* w = reinterpret_cast<const float2*>(d.w);
-    for (int i = threadIdx.x; i < kStationChunk * kBeamGroup; i += kThreads) {
+    for (int i = threadIdx.x; i < kStationChunk * kBeamGroup; i += blockDim.x) {
         const int sl = i % kStationChunk, bl = i / kStationChunk;
         const int s = s0 + sl, b = b0 + bl;
         float2 v = make_float2(0.f, 0.f);
@@ -212,7 +251,7 @@ LBF_INLINE void stage_weights_f32(float* wl, const BlockDesc& d, int c, int b0, 
 // words (64 stations + a 16-byte pad against LDS bank conflicts).
 LBF_INLINE void stage_weights_h(uint32_t* wh, const BlockDesc& d, int c, int b0, int s0) {
     const uint32_t* w = reinterpret_cast<const uint32_t*>(d.w);
-    for (int i = threadIdx.x; i < kStationChunk * kBeamGroup; i += kThreads) {
+    for (int i = threadIdx.x; i < kStationChunk * kBeamGroup; i += blockDim.x) {
         const int sl = i % kStationChunk, bl = i / kStationChunk;
         const int s = s0 + sl, b = b0 + bl;
         uint32_t v = 0u;
@@ -311,6 +350,23 @@ LBF_INLINE void stokes_sums(const floatx16 (&acc)[4], int k0, float (&s)[4]) {
             s[2] = __builtin_fmaf(xi, yi, __builtin_fmaf(xr, yr, s[2]));
             s[3] = __builtin_fmaf(-xr, yi, __builtin_fmaf(xi, yr, s[3]));
         }
+    }
+}
+
+// add sample k of a tile to the Stokes sums s (as stokes_sums, one sample)
+template <int PR>
+LBF_INLINE void stokes_add(const floatx16 (&acc)[4], int k, float (&s)[4]) {
+    const float xr = acc[0][k], xi = acc[1][k], yr = acc[2][k], yi = acc[3][k];
+    if (PR == PR_I) {
+        s[0] = __builtin_fmaf(xr, xr, s[0]);
+        s[0] = __builtin_fmaf(xi, xi, s[0]);
+        s[0] = __builtin_fmaf(yr, yr, s[0]);
+        s[0] = __builtin_fmaf(yi, yi, s[0]);
+    } else {
+        s[0] = __builtin_fmaf(xi, xi, __builtin_fmaf(xr, xr, s[0]));
+        s[1] = __builtin_fmaf(yi, yi, __builtin_fmaf(yr, yr, s[1]));
+        s[2] = __builtin_fmaf(xi, yi, __builtin_fmaf(xr, yr, s[2]));
+        s[3] = __builtin_fmaf(-xr, yi, __builtin_fmaf(xi, yr, s[3]));
     }
 }
 
@@ -421,6 +477,70 @@ LBF_INLINE void stokes_store_bfast(const floatx16 (&acc)[4], const EpiCtx& e, in
     }
 }
 
+// Branch-free stores of the fast FP16/BF16 worker.  rs covers one channel of
+// the output; a lane with nothing to store (beam >= B, sample past the end,
+// no tile) uses an offset past the end of the buffer, which the hardware
+// drops, so the epilogue has no control flow and interleaves freely with the
+// MFMAs of the next tile.  The offset is 2^31, not 2^32 - 1: the range check
+// adds the access size to the offset, and the latter would wrap around to an
+// in-range value.  Buffers are below 2^31 bytes (checked by the launcher).
+constexpr uint32_t kNoStore = 0x80000000u;
+
+// off if ok, else kNoStore, as a lane select the compiler keeps (a plain ?:
+// is turned into a branch around the store)
+LBF_INLINE uint32_t store_off(bool ok, uint32_t off) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(ok);
+    uint32_t r;
+    __asm__("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(kNoStore), "v"(off), "s"(m));
+    return r;
+}
+
+LBF_INLINE __amdgpu_buffer_rsrc_t channel_rsrc(void* out, int c, uint32_t bytes_per_channel) {
+    const uint64_t base = reinterpret_cast<uint64_t>(out) + (uint64_t)c * bytes_per_channel;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0,
+                                             (int)bytes_per_channel, 0x00020000);
+}
+
+// Stokes of one 32x32 tile into channel-major s[k][t'][b] of its channel
+template <int PR, int TI>
+LBF_INLINE void stokes_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t rs, int B, int T2, int beam, int t0,
+                                int h, bool ok) {
+    constexpr int K = PR == PR_IQUV ? 4 : 1;
+    constexpr int NOUT = 16 / TI;
+    const int tq0 = (t0 + 16 * h) / TI;
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        float sm[4], v[4];
+        stokes_sums<PR, TI>(acc, o * TI, sm);
+        stokes_from_sums<PR>(sm, v);
+        const int tq = tq0 + o;
+        const bool st = ok && tq < T2;
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+            const uint32_t off = store_off(st, (((uint32_t)kk * T2 + tq) * (uint32_t)B + beam) * 4u);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[kk]), rs, (int)off, 0, 0);
+        }
+    }
+}
+
+// complex voltages of one tile into y[b][t][p] of its channel
+LBF_INLINE void volt_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t rs, int T, int beam, int t0, int h,
+                              bool ok) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int t = t0 + 16 * h + k;
+        const uint32_t off = store_off(ok && t < T, ((uint32_t)beam * T + t) * 16u);
+        floatx4 v;
+        v[0] = acc[0][k];
+        v[1] = acc[1][k];
+        v[2] = acc[2][k];
+        v[3] = acc[3][k];
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs, (int)off, 0, 0);
+    }
+}
+
 // fast workers: t_int fixed at compile time, f_int == 1
 template <int PR, int TI>
 LBF_INLINE void epilogue_tiles_fixed(const floatx16 (&acc)[kBeamTiles][4], const EpiCtx& e, int b0, int r, int t0,
@@ -524,10 +644,15 @@ LBF_INLINE WaveTiles wave_tiles(int wave, int T, int t_int) {
     return w;
 }
 
-// work items of the fast FP16/BF16 worker: (channel, super-group of 512 beams)
-inline int block_items_fast_h(const BlockDesc& d, int* nsg) {
-    *nsg = (d.B + kSuperGroup - 1) / kSuperGroup;
-    return d.C * *nsg;
+// Sample streams of the fast FP16/BF16 worker: one for more than 128 beams
+// (work items of 256 beams), else two (items of 128 beams).
+__host__ __device__ inline int fast_h_streams(const BlockDesc& d) { return d.B > 128 ? 1 : 2; }
+
+// work items of the fast FP16/BF16 worker: (channel, group of 256/NS beams)
+inline int block_items_fast_h(const BlockDesc& d, int* nbg) {
+    const int per = 8 / fast_h_streams(d) * kTile;
+    *nbg = (d.B + per - 1) / per;
+    return d.C * *nbg;
 }
 
 // number of (channel group, beam group) work items of a block
@@ -537,7 +662,7 @@ inline int block_items(const BlockDesc& d, int* nbg) {
     return ngroups_c * *nbg;
 }
 
-__host__ __device__ inline int sample_bytes(int xtype) { return xtype == XT_CI8 ? 4 : xtype == XT_CI16 ? 8 : 16; }
+__host__ __device__ constexpr int sample_bytes(int xtype) { return xtype == XT_CI8 ? 4 : xtype == XT_CI16 ? 8 : 16; }
 
 // The fast workers take up to 64 stations of complex int8/int16 samples,
 // voltages or Stokes with t_int <= 16 and no channel integration, and 8
@@ -546,7 +671,11 @@ __host__ __device__ inline int sample_bytes(int xtype) { return xtype == XT_CI8 
 __host__ __device__ inline bool fast_path(const BlockDesc& d) {
     if (d.S > kStationChunk || d.xtype == XT_CF32) return false;
     if (d.product != PR_VOLT && (d.t_int > 16 || d.f_int != 1)) return false;
-    return 8.0 * (double)d.C * (double)d.T * sample_bytes(d.xtype) < 2147483648.0;
+    // one channel's output (addressed with 32-bit buffer offsets, 2^31 = "no store")
+    const double out_ch = d.product == PR_VOLT ? 16.0 * d.B * (double)d.T
+                                               : 4.0 * d.product * d.B * (double)(d.T / d.t_int);
+    if (out_ch >= 2147483648.0 - 4096.0) return false;
+    return 8.0 * (double)d.C * (double)d.T * sample_bytes(d.xtype) < 2147483648.0 - 4096.0;
 }
 
 // Buffer resource over the samples of stations [s0, s0+8) of channel c

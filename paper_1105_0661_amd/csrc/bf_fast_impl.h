@@ -12,10 +12,11 @@ __global__ __launch_bounds__(kThreads) void bf_f32_fast_kernel(BlockDesc d, int 
     item_f32_fast<XT, PR, TI>(d, xcd_remap(blockIdx.x, nitems), nbg, wl);
 }
 
-template <int XT, int CT, int PR, int TI, int NK>
-__global__ __launch_bounds__(kThreads) void bf_h_fast_kernel(BlockDesc d, int nsg, int nitems) {
-    __shared__ __attribute__((aligned(16))) uint32_t wh[kWhWords];
-    item_h_fast<XT, CT, PR, TI, NK>(d, xcd_remap(blockIdx.x, nitems), nsg, wh);
+// 8 waves, two per SIMD; LDS: NS streams x 2 buffers of one A tile
+template <int XT, int CT, int PR, int TI, int NK, int NS>
+__global__ __launch_bounds__(kThreadsH) void bf_h_fast_kernel(BlockDesc d, int nbg, int nitems) {
+    __shared__ __attribute__((aligned(16))) uint32_t at[NS * 2 * kATileWords];
+    item_h_fast<XT, CT, PR, TI, NK, NS>(d, xcd_remap(blockIdx.x, nitems), nbg, at);
 }
 
 // launch one instantiation; PR/TI/NK chosen from the block by the callers
@@ -46,10 +47,14 @@ inline hipError_t launch_f32_xt(const BlockDesc& d, int nbg, int n, hipStream_t 
 
 template <int XT, int CT, int PR, int TI>
 inline hipError_t launch_h_k(const BlockDesc& d, int nbg, int n, hipStream_t st) {
-    if (d.S <= 32)
-        hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4>), dim3(n), dim3(kThreads), 0, st, d, nbg, n);
-    else
-        hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8>), dim3(n), dim3(kThreads), 0, st, d, nbg, n);
+    const dim3 g(n), b(kThreadsH);
+    if (fast_h_streams(d) == 1) {
+        if (d.S <= 32) hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4, 1>), g, b, 0, st, d, nbg, n);
+        else hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8, 1>), g, b, 0, st, d, nbg, n);
+    } else {
+        if (d.S <= 32) hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4, 2>), g, b, 0, st, d, nbg, n);
+        else hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8, 2>), g, b, 0, st, d, nbg, n);
+    }
     return hipGetLastError();
 }
 

@@ -96,91 +96,262 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* wl) 
     }
 }
 
-// FP16/BF16 operands (MFMA 32x32x16: 8 stations per step).  NK = K-steps
-// (8-station groups) covering the stations.  A work item is one channel and
-// a super-group of up to 512 beams: the 4 waves split into BW beam groups of
-// 128 beams (weights of all of them in LDS) times 4/BW sample streams, so a
-// channel's samples are read once and the XCD-aware item order puts 32
-// adjacent channels -- one full 128-byte line of the beam-major output -- on
-// each XCD at a time.  Lane half h takes stations 8kk + 4h + i of K-step kk.
-template <int XT, int CT, int PR, int TI, int NK>
-LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nsg, uint32_t* wh) {
-    typedef Raw<XT> R;
-    typedef typename R::type RT;
-    typedef typename MfmaH<CT>::vec V;
-    constexpr int BYTES = sizeof(RT);
-    const int c = item / nsg, sg = item % nsg;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int r = lane & 31, h = lane >> 5;
-    const int S = d.S, T = d.T;
-    const int bsg0 = sg * kSuperGroup;
-    const int nb = min(kSuperGroup, d.B - bsg0);
-    const int BW = nb <= kBeamGroup ? 1 : (nb <= 2 * kBeamGroup ? 2 : 4);
-    const int TW = kWavesPerGroup / BW;
-    const int bw = wave % BW, tw = wave / BW;
-    const int b0 = bsg0 + bw * kBeamGroup;
-    EpiCtx e = make_epi(d, PR, c);
-    e.c = c;
-    e.first = 1;
-    const int ntiles = (T + kTile - 1) / kTile;
-    const int ntw = ntiles > tw ? (ntiles - tw + TW - 1) / TW : 0;
-    const int trow = tile_row_sample(r);
-    const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
-    const uint32_t hoff = (uint32_t)h * 4u * stride_bytes;
-    const int wbase = bw * kBeamGroup * kWRow;
+// FP16/BF16 operands (MFMA 32x32x16: 8 stations per K-step, NK K-steps).
+//
+// A work group of 8 waves (two per SIMD) takes one channel and NBT = 8/NS
+// beam tiles of 32 beams; its tiles of 32 samples are split into NS streams.
+// Each wave owns one beam tile and keeps that tile's weights for all K-steps
+// in registers, as two variants  wr = (w_re, -w_im),  wi = (w_im, w_re),  so
+// that with the plain sample operand a = (x_re, x_im) along K
+//     Re y = a . wr,   Im y = a . wi.
+// The samples of each 32-sample tile are loaded once per work group with
+// 16-byte loads, converted once, and left in LDS (double buffered, one
+// barrier per step) for all beam tiles to read.  Waves 4-7 defer each tile's
+// Stokes epilogue to the next step, so on every SIMD one wave's epilogue
+// (VALU) runs while the other wave's MFMAs do.
+constexpr int kThreadsH = 512;
+constexpr int kARow = 68;                          // words per (sample, polarisation) row of an A tile
+constexpr int kATileWords = kTile * 2 * kARow;     // 17 KB
 
-    for (int g = 0; g < BW; ++g) stage_weights_h_fast(wh + g * kBeamGroup * kWRow, d, c, bsg0 + g * kBeamGroup);
-    __syncthreads();
+// Word of station s, polarisation p, sample t (0..31) in an A tile.  Groups of
+// 4 stations are XOR-swizzled by a_swz(t) so that neither the loaders' stores
+// (lanes 4 samples apart for 8 consecutive t/4) nor the MFMA operand reads
+// (lanes at samples t, t + 16 of the row map) collide in the banks; a lane
+// still reads its 4 stations as one aligned 16-byte word.
+LBF_INLINE int a_swz(int t) { return ((t >> 2) & 7) ^ ((t >> 4) & 1); }
+LBF_INLINE int a_word(int t, int p, int s) { return (2 * t + p) * kARow + 4 * ((s >> 2) ^ a_swz(t)) + (s & 3); }
+
+// 16 bytes of one station's consecutive samples -> operand words of sample j
+template <int XT, int CT> struct Chunk;
+template <int CT> struct Chunk<XT_CI8, CT> {
+    static constexpr int samples = 4;
+    LBF_INLINE static void xy(const u32x4& v, int j, uint32_t& fx, uint32_t& fy) {
+        Conv2<XT_CI8, CT>::xy((int)v[j], fx, fy);
+    }
+};
+template <int CT> struct Chunk<XT_CI16, CT> {
+    static constexpr int samples = 2;
+    LBF_INLINE static void xy(const u32x4& v, int j, uint32_t& fx, uint32_t& fy) {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 w = {v[2 * j], v[2 * j + 1]};
+        Conv2<XT_CI16, CT>::xy(__builtin_bit_cast(shortx4, w), fx, fy);
+    }
+};
+
+template <int XT, int CT, int PR, int TI, int NK, int NS>
+LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at) {
+    typedef typename MfmaH<CT>::vec V;
+    constexpr int BYTES = sample_bytes(XT);
+    constexpr int NBT = 8 / NS;                            // beam tiles per item
+    constexpr int SPC = Chunk<XT, CT>::samples;            // samples per 16-byte chunk
+    constexpr int CPS = kTile / SPC;                       // chunks per station per tile
+    constexpr int CPTILE = 8 * NK * CPS;                   // chunks per tile
+    constexpr int CPT = (NS * CPTILE + kThreadsH - 1) / kThreadsH;   // chunks per thread per step
+    const int c = item / nbg, bg = item % nbg;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int r = lane & 31, h = lane >> 5;
+    const int bt = wave % NBT, sigma = wave / NBT;         // beam tile, sample stream
+    const int S = d.S, T = d.T, B = d.B;
+    const int beam = (bg * NBT + bt) * kTile + r;
+    const int ntiles = (T + kTile - 1) / kTile;
+    const int nsteps = (ntiles + NS - 1) / NS;
+    const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
+    constexpr int K = PR == PR_IQUV ? 4 : 1;
+    const int T2 = PR == PR_VOLT ? T : T / TI;
+    const __amdgpu_buffer_rsrc_t ors =
+        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)K * T2 * B * 4u);
+
+    // this wave's weights, both variants, all K-steps
+    u32x4 wr[NK], wi[NK];
     {
-        // Rolling prefetch: slot kk holds K-step kk of the current tile until
-        // it is converted, then is refilled with K-step kk of the next tile,
-        // so every load has a whole tile of MFMAs to arrive.
-        RT buf[NK][4];
-        auto load_step = [&](int tile, int kk) {
-            const uint32_t off = hoff + (uint32_t)min(tile * kTile + trow, T - 1) * BYTES;
-            const __amdgpu_buffer_rsrc_t rs = station_group_rsrc(d.x, BYTES, 8 * kk, S, c, T, stride_bytes);
+        const __amdgpu_buffer_rsrc_t rs = weight_rsrc(d, c, 4);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) buf[kk][i] = buffer_sample<XT>(rs, off + (uint32_t)i * stride_bytes);
-        };
-        if (ntw > 0) {
+        for (int kk = 0; kk < NK; ++kk) {
+            const u32x4 w = __builtin_bit_cast(
+                u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(((uint32_t)beam * S + 8 * kk + 4 * h) * 4u), 0, 0));
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) load_step(tw, kk);
+            for (int i = 0; i < 4; ++i) {
+                wr[kk][i] = neg_hi(w[i]);
+                wi[kk][i] = swap16(w[i]);
+            }
         }
-        for (int k = 0; k < ntw; ++k) {
-            const int t0 = (tw + TW * k) * kTile;
-            const int tnext = tw + TW * (k + 1 < ntw ? k + 1 : k);
-            // read the weight fragments from LDS inside the tile loop: kept
-            // live across tiles they would take 128 VGPRs
-            int widx = wbase + r * kWRow + 4 * h;
-            __asm__ volatile("" : "+v"(widx));
-            const uint32_t* wrow = wh + widx;
-            floatx16 acc[kBeamTiles][4];
+    }
+
+    // loaders: chunk j = tid + 512 i of a step covers stream j / CPTILE,
+    // station (j % CPTILE) / CPS and samples SPC * (j % CPS) + [0, SPC)
+    u32x4 raw[CPT];
+    auto load_chunks = [&](int k) {
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) {
-                APair p[4];
+        for (int i = 0; i < CPT; ++i) {
+            const int j = tid + kThreadsH * i;
+            const int sg = j / CPTILE, jt = j % CPTILE, s = jt / CPS, q = jt % CPS;
+            const int tile = min(sg + NS * k, ntiles - 1);
+            // descriptor over the whole planes of the group's stations, the
+            // channel in the offset: a ragged last tile reads past the end of
+            // the channel into the next one, or past the last valid station
+            // (out of range: zeros), never past the array
+            const __amdgpu_buffer_rsrc_t rs = station_group_rsrc(d.x, BYTES, s & ~7, S, 0, T, stride_bytes);
+            const uint32_t off = (uint32_t)(s & 7) * stride_bytes + (uint32_t)(c * T + tile * kTile + q * SPC) * BYTES;
+            raw[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+        }
+    };
+    auto store_chunk = [&](int k, int i) {
+        const int j = tid + kThreadsH * i;
+        const int sg = j / CPTILE, jt = j % CPTILE, s = jt / CPS, q = jt % CPS;
+        if (NS * CPTILE % kThreadsH == 0 || j < NS * CPTILE) {
+            uint32_t* ab = at + (sg * 2 + (k & 1)) * kATileWords;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) p[i] = Conv<XT, CT>::frag(buf[kk][i]);
-                load_step(tnext, kk);
-                const u32x4 uxr = {p[0].xr, p[1].xr, p[2].xr, p[3].xr};
-                const u32x4 uxi = {p[0].xi, p[1].xi, p[2].xi, p[3].xi};
-                const u32x4 uyr = {p[0].yr, p[1].yr, p[2].yr, p[3].yr};
-                const u32x4 uyi = {p[0].yi, p[1].yi, p[2].yi, p[3].yi};
-                const V axr = __builtin_bit_cast(V, uxr), axi = __builtin_bit_cast(V, uxi);
-                const V ayr = __builtin_bit_cast(V, uyr), ayi = __builtin_bit_cast(V, uyi);
-                V bfr[kBeamTiles];
+            for (int js = 0; js < SPC; ++js) {
+                uint32_t fx, fy;
+                Chunk<XT, CT>::xy(raw[i], js, fx, fy);
+                const int t = q * SPC + js;
+                ab[a_word(t, 0, s)] = fx;
+                ab[a_word(t, 1, s)] = fy;
+            }
+        }
+    };
+
+    // One step k, written out in the order it should run: K-step kk's four
+    // MFMAs (operands read one K-step ahead from LDS), then 1/NK of the
+    // epilogue of step k-1 from the other accumulator set, with scheduling
+    // barriers between the slices so that the compiler keeps the VALU work
+    // next to the MFMAs it is meant to overlap (a wave's own VALU
+    // instructions run while its MFMAs do; another wave's on the same SIMD do
+    // not).  The samples of step k+1 are loaded at the start and staged in
+    // the last two slices.
+    const int trow = tile_row_sample(r);
+    const int sw = a_swz(trow);
+    constexpr int SPS = 16 / NK;                           // epilogue samples per slice
+    constexpr bool PIPE = !(XT == XT_CI16 && NS == 2);     // two accumulator sets
+    constexpr int NOUT = PR == PR_VOLT ? 1 : 16 / TI;
+    auto step = [&](int k, floatx16 (&acc)[4], const floatx16 (&prev)[4]) {
+        load_chunks(k + 1);
+        int rowx = (sigma * 2 + (k & 1)) * kATileWords + 2 * trow * kARow;
+        __asm__ volatile("" : "+v"(rowx));
+        const uint32_t* ax0 = at + rowx;
+        u32x4 ax[2], ay[2];
+        ax[0] = *reinterpret_cast<const u32x4*>(ax0 + 4 * (h ^ sw));
+        ay[0] = *reinterpret_cast<const u32x4*>(ax0 + kARow + 4 * (h ^ sw));
+        const int tprev = sigma + NS * (k - 1);
+        const bool okprev = k >= 1 && tprev < ntiles && beam < B;
+        float sm[NOUT][4];
 #pragma unroll
-                for (int a = 0; a < kBeamTiles; ++a)
-                    bfr[a] = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(wrow + a * kTile * kWRow + 8 * kk));
+        for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-                for (int a = 0; a < kBeamTiles; ++a) {
-                    acc[a][0] = MfmaH<CT>::mfma(axr, bfr[a], kk == 0 ? zero16() : acc[a][0]);
-                    acc[a][1] = MfmaH<CT>::mfma(axi, bfr[a], kk == 0 ? zero16() : acc[a][1]);
-                    acc[a][2] = MfmaH<CT>::mfma(ayr, bfr[a], kk == 0 ? zero16() : acc[a][2]);
-                    acc[a][3] = MfmaH<CT>::mfma(ayi, bfr[a], kk == 0 ? zero16() : acc[a][3]);
+            for (int q = 0; q < 4; ++q) sm[o][q] = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) {
+            if (kk + 1 < NK) {
+                const int off = 4 * ((2 * (kk + 1) + h) ^ sw);
+                ax[(kk + 1) & 1] = *reinterpret_cast<const u32x4*>(ax0 + off);
+                ay[(kk + 1) & 1] = *reinterpret_cast<const u32x4*>(ax0 + kARow + off);
+            }
+            const V a = __builtin_bit_cast(V, ax[kk & 1]), b = __builtin_bit_cast(V, ay[kk & 1]);
+            const V br = __builtin_bit_cast(V, wr[kk]), bi = __builtin_bit_cast(V, wi[kk]);
+            acc[0] = MfmaH<CT>::mfma(a, br, kk == 0 ? zero16() : acc[0]);
+            acc[1] = MfmaH<CT>::mfma(a, bi, kk == 0 ? zero16() : acc[1]);
+            acc[2] = MfmaH<CT>::mfma(b, br, kk == 0 ? zero16() : acc[2]);
+            acc[3] = MfmaH<CT>::mfma(b, bi, kk == 0 ? zero16() : acc[3]);
+            // epilogue slice: samples [kk SPS, (kk+1) SPS) of the previous tile
+#pragma unroll
+            for (int js = 0; js < SPS; ++js) {
+                const int smp = kk * SPS + js;
+                if (PR == PR_VOLT) {
+                    const int t = tprev * kTile + 16 * h + smp;
+                    const uint32_t off = store_off(okprev && t < T, ((uint32_t)beam * T + t) * 16u);
+                    floatx4 v;
+                    v[0] = prev[0][smp];
+                    v[1] = prev[1][smp];
+                    v[2] = prev[2][smp];
+                    v[3] = prev[3][smp];
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), ors, (int)off, 0, 0);
+                } else {
+                    stokes_add<PR>(prev, smp, sm[smp / TI]);
                 }
             }
-            epilogue_tiles_fixed<PR, TI>(acc, e, b0, r, t0, h);
+            if (kk >= NK - 2) {                              // stage step k+1's samples
+#pragma unroll
+                for (int i = 0; i < CPT; ++i)
+                    if (i % 2 == kk - (NK - 2)) store_chunk(k + 1, i);
+            }
+            // keep this slice's sums here (left alone, the compiler sinks the
+            // whole epilogue below the last MFMA)
+            if (PR != PR_VOLT) {
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) __asm__ volatile("" : "+v"(sm[o][q]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
+        if (PR != PR_VOLT) {
+            const int tq0 = (tprev * kTile + 16 * h) / TI;
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) {
+                float v[4];
+                stokes_from_sums<PR>(sm[o], v);
+                const int tq = tq0 + o;
+#pragma unroll
+                for (int kq = 0; kq < K; ++kq) {
+                    const uint32_t off = store_off(okprev && tq < T2, (((uint32_t)kq * T2 + tq) * (uint32_t)B + beam) * 4u);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[kq]), ors, (int)off, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    };
+    // the last tile's epilogue: one more step without MFMAs
+    auto final_epilogue = [&](const floatx16 (&prev)[4], int klast) {
+        const int tile = sigma + NS * klast;
+        const bool ok = klast >= 0 && tile < ntiles && beam < B;
+        if (PR == PR_VOLT) volt_store_cm(prev, ors, T, beam, tile * kTile, h, ok);
+        else stokes_store_cm<PR, TI>(prev, ors, B, T2, beam, tile * kTile, h, ok);
+    };
+
+    load_chunks(0);
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) store_chunk(0, i);
+    __syncthreads();
+    if (!PIPE) {
+        // one accumulator set (complex int16 with two streams: the loaders'
+        // registers leave no room for a second): MFMAs, then the epilogue
+        floatx16 acc[4];
+        for (int k = 0; k < nsteps; ++k) {
+            load_chunks(k + 1);
+            int rowx = (sigma * 2 + (k & 1)) * kATileWords + 2 * trow * kARow;
+            __asm__ volatile("" : "+v"(rowx));
+            const uint32_t* ax0 = at + rowx;
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) {
+                const int off = 4 * ((2 * kk + h) ^ sw);
+                const V a = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(ax0 + off));
+                const V b = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(ax0 + kARow + off));
+                const V br = __builtin_bit_cast(V, wr[kk]), bi = __builtin_bit_cast(V, wi[kk]);
+                acc[0] = MfmaH<CT>::mfma(a, br, kk == 0 ? zero16() : acc[0]);
+                acc[1] = MfmaH<CT>::mfma(a, bi, kk == 0 ? zero16() : acc[1]);
+                acc[2] = MfmaH<CT>::mfma(b, br, kk == 0 ? zero16() : acc[2]);
+                acc[3] = MfmaH<CT>::mfma(b, bi, kk == 0 ? zero16() : acc[3]);
+            }
+            final_epilogue(acc, k);
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) store_chunk(k + 1, i);
+            __syncthreads();
+        }
+        return;
+    }
+    floatx16 acc0[4], acc1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc1[q] = zero16();
+    int k = 0;
+    for (; k + 1 < nsteps; k += 2) {
+        step(k, acc0, acc1);
+        step(k + 1, acc1, acc0);
+    }
+    if (k < nsteps) {
+        step(k, acc0, acc1);
+        final_epilogue(acc0, k);
+    } else {
+        final_epilogue(acc1, k - 1);
     }
 }
 
@@ -203,12 +374,13 @@ LBF_INLINE void item_f32_generic(const BlockDesc& d, int item, int nbg, float* w
     const int ngroups = (ntiles + tpg - 1) / tpg;
     const int trow = tile_row_sample(r);
     const size_t stride = (size_t)C * T;
+    const int nw = blockDim.x / kWave;          // waves sharing the groups
 
     for (int j = 0; j < f_int; ++j) {
         const int c = g * f_int + j;
         e.c = c;
         e.first = j == 0;
-        for (int grp0 = 0; grp0 < ngroups; grp0 += kWavesPerGroup) {
+        for (int grp0 = 0; grp0 < ngroups; grp0 += nw) {
             const int grp = grp0 + wave;
             const bool active = grp < ngroups;
             float gs[kBeamTiles][4];
@@ -283,12 +455,13 @@ LBF_INLINE void item_h_generic(const BlockDesc& d, int item, int nbg, uint32_t* 
     const int ngroups = (ntiles + tpg - 1) / tpg;
     const int trow = tile_row_sample(r);
     const size_t stride = (size_t)C * T;
+    const int nw = blockDim.x / kWave;          // waves sharing the groups
 
     for (int j = 0; j < f_int; ++j) {
         const int c = g * f_int + j;
         e.c = c;
         e.first = j == 0;
-        for (int grp0 = 0; grp0 < ngroups; grp0 += kWavesPerGroup) {
+        for (int grp0 = 0; grp0 < ngroups; grp0 += nw) {
             const int grp = grp0 + wave;
             const bool active = grp < ngroups;
             float gs[kBeamTiles][4];

@@ -268,7 +268,12 @@ def test_incoherent_beam_matches_oracle():
 @pytest.mark.parametrize("ctype", [lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
 def test_batch_equals_single_launches_bitwise(ctype):
     torch = _torch()
-    specs = [(24, 17, 2, 4, 64, "ci8", lbf.STOKES_I, 16, 1), (40, 150, 1, 8, 96, "ci16", lbf.STOKES_IQUV, 16, 2),
+    # batch-kernel blocks (t_int 16, no channel integration): one and two
+    # sample streams (more / at most 128 beams), 4 and 8 K-steps, ragged T;
+    # the rest run through their own launches
+    specs = [(24, 17, 2, 4, 64, "ci8", lbf.STOKES_I, 16, 1), (29, 130, 2, 3, 208, "ci8", lbf.STOKES_IQUV, 16, 1),
+             (33, 200, 1, 4, 112, "ci16", lbf.STOKES_I, 16, 1), (64, 40, 2, 4, 176, "ci16", lbf.STOKES_IQUV, 16, 1),
+             (40, 150, 1, 8, 96, "ci16", lbf.STOKES_IQUV, 16, 2),
              (64, 33, 3, 2, 32, "ci8", lbf.STOKES_IQUV, 32, 1), (31, 1, 1, 5, 48, "ci16", lbf.STOKES_I, 4, 1)]
     items, singles, refs = [], [], []
     for i, (S, B, nsb, nch, T, xt, prod, ti, fi) in enumerate(specs):
