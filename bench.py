@@ -151,11 +151,13 @@ def batched(lbf, torch, jobs, steps, warmup):
 
     ms_batch = run(lambda: lbf.beamform_batch(items))
     ms_seq = run(lambda: [lbf.beamform(*it[:5], out=it[5]) for it in items])
+    per_job = [run(lambda it=it: lbf.beamform(*it[:5], out=it[5])) for it in items]
     return {"workload": "12 concurrent one-second observations: stations U{24..64}, beams U{1..400}, "
                         "16/64/256 channels x U{8..64} subbands, ci8/ci16, Stokes I or IQUV x16, FP16 MFMA, "
                         "one persistent launch",
             "jobs": [{"S": j["spec"].S, "B": j["spec"].B, "C": int(j["x"].shape[1]), "T": j["spec"].T,
-                      "xtype": j["spec"].xtype, "product": j["spec"].product} for j in jobs],
+                      "xtype": j["spec"].xtype, "product": j["spec"].product, "ms_alone": pj}
+                     for j, pj in zip(jobs, per_job)],
             "ms_per_batch": ms_batch, "ms_sequential": ms_seq,
             "beam_samples_per_s": bs / (ms_batch / 1e3), "TFLOPs": fl / (ms_batch / 1e3) / 1e12,
             "roofline_ms": froof * 1e3, "roofline_frac": froof * 1e3 / ms_batch,
@@ -399,6 +401,7 @@ def main():
         log("batched: %.3f ms per batch, %.3g beam-samples/s, %.2f of roofline, %.2fx sequential"
             % (batch_res["ms_per_batch"], batch_res["beam_samples_per_s"], batch_res["roofline_frac"],
                batch_res["batch_vs_sequential"]))
+        log("batched, per job alone (ms): %s" % ["%.3f" % jb["ms_alone"] for jb in batch_res["jobs"]])
         serve_res = serving(lbf, torch, synth, jobs, blk, x, b2, x2, a.serve_seconds, 2.0)
         log("serving: %s" % serve_res["open_loop"])
         log("serving closed loop: %s" % serve_res["closed_loop"])

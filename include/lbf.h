@@ -75,7 +75,8 @@ const char* lbf_version(void);
  *   d_w           [C][B][S] complex of wtype (complex f32: 8 bytes; complex
  *                 f16 / bf16: 4 bytes per weight)
  *   d_tau         [B][S] f64 seconds, or NULL
- * Errors: LBF_E_INVAL for sizes < 1, NULL d_* inputs/outputs, unknown wtype.
+ * Errors: LBF_E_INVAL for sizes < 1, NULL d_* inputs/outputs, unknown wtype,
+ * B*S above 2^30 or C above 2097120.
  */
 int lbf_compute_weights(const double* d_station_xyz, int S, const double* d_beam_dir, int B,
                         const double* ref_dir, const double* d_freq_hz, int C, int wtype,

@@ -126,6 +126,8 @@ int lbf_compute_weights(const double* d_station_xyz, int S, const double* d_beam
     if (!d_station_xyz || !d_beam_dir || !d_freq_hz || !d_w)
         return fail(LBF_E_INVAL, "lbf_compute_weights: NULL device pointer");
     if (wtype < LBF_F32 || wtype > LBF_BF16) return fail(LBF_E_INVAL, "lbf_compute_weights: unknown wtype %d", wtype);
+    if ((long long)B * S > (1LL << 30) || C > 65535 * 32)
+        return fail(LBF_E_INVAL, "lbf_compute_weights: too large (B*S=%lld, C=%d)", (long long)B * S, C);
     const double rx = ref_dir ? ref_dir[0] : 0.0, ry = ref_dir ? ref_dir[1] : 0.0, rz = ref_dir ? ref_dir[2] : 0.0;
     hipError_t e = lbf::launch_weights(d_station_xyz, S, d_beam_dir, B, rx, ry, rz, d_freq_hz, C, wtype, d_w, d_tau,
                                        (hipStream_t)stream);

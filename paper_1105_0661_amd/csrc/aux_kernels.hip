@@ -10,30 +10,34 @@ namespace lbf {
 // for beam b, tau = p_s . (u_b - u_ref) / c0, and the phase-shift weight
 // w = exp(-2 pi i frac(f tau)).  Everything up to the final rounding is FP64:
 // f * tau spans many turns and only its fractional part matters.
-// One thread per (c, b, s), s fastest, so stores are coalesced.
+// One thread per (b, s) and group of kWChan channels: tau once, then one
+// weight per channel; threads of a block are consecutive (b, s), so each
+// channel's stores are coalesced.
 // ---------------------------------------------------------------------------
 constexpr double kC0 = 299792458.0;
+constexpr int kWChan = 32;
 
 template <int WT>
 __global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__ pos, int S,
                                                       const double* __restrict__ dir, int B, double rx, double ry,
                                                       double rz, const double* __restrict__ freq, int C, void* w,
                                                       double* tau) {
-    const size_t n = (size_t)C * B * S;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int s = (int)(i % S);
-        const size_t cb = i / S;
-        const int b = (int)(cb % B);
-        const int c = (int)(cb / B);
-        const double dx = dir[3 * b + 0] - rx, dy = dir[3 * b + 1] - ry, dz = dir[3 * b + 2] - rz;
-        const double proj = pos[3 * s + 0] * dx + pos[3 * s + 1] * dy + pos[3 * s + 2] * dz;
-        const double t = proj / kC0;
-        if (tau != nullptr && c == 0) tau[(size_t)b * S + s] = t;
+    const int bs = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bs >= B * S) return;
+    const int b = bs / S, s = bs - b * S;
+    const double dx = dir[3 * b + 0] - rx, dy = dir[3 * b + 1] - ry, dz = dir[3 * b + 2] - rz;
+    const double proj = pos[3 * s + 0] * dx + pos[3 * s + 1] * dy + pos[3 * s + 2] * dz;
+    const double t = proj / kC0;
+    if (tau != nullptr && blockIdx.y == 0) tau[bs] = t;
+    const int c0 = blockIdx.y * kWChan, c1 = min(C, c0 + kWChan);
+    const size_t BS = (size_t)B * S;
+    for (int c = c0; c < c1; ++c) {
         const double m = freq[c] * t;
         const double r = m - rint(m);          // fractional turn in [-0.5, 0.5]
         double sn, cs;
         sincospi(2.0 * r, &sn, &cs);
         const double wr = cs, wi = -sn;
+        const size_t i = (size_t)c * BS + bs;
         if (WT == CT_F32) {
             float2 v;
             v.x = (float)wr;
@@ -49,10 +53,8 @@ __global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__
 
 hipError_t launch_weights(const double* pos, int S, const double* dir, int B, double rx, double ry, double rz,
                           const double* freq, int C, int wtype, void* w, double* tau, hipStream_t st) {
-    const size_t n = (size_t)C * B * S;
-    size_t blocks = (n + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    dim3 g((unsigned)blocks), b(256);
+    const int bs = B * S;
+    dim3 g((unsigned)((bs + 255) / 256), (unsigned)((C + kWChan - 1) / kWChan)), b(256);
     if (wtype == CT_F32) hipLaunchKernelGGL(weights_kernel<CT_F32>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, freq, C, w, tau);
     else if (wtype == CT_F16) hipLaunchKernelGGL(weights_kernel<CT_F16>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, freq, C, w, tau);
     else hipLaunchKernelGGL(weights_kernel<CT_BF16>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, freq, C, w, tau);
@@ -159,30 +161,62 @@ hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int el
 
 // ---------------------------------------------------------------------------
 // Beam-fastest staging s[c][m][b] -> final order out[b][m][c] (m = k*T' + t',
-// Section 4.6).  Tiles of 32 channels x 64 beams per m go through LDS: reads
-// are 256-byte runs along b, writes 128-byte runs along c.
+// Section 4.6).  Each work group moves a 64-channel x 64-beam tile of one m
+// through LDS: reads are 256-byte runs along b, writes 256-byte runs along c,
+// 16 bytes per lane where the rows allow it (VEC: B and C2 multiples of 4).
 // ---------------------------------------------------------------------------
+template <bool VEC>
 __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* __restrict__ in, int C2, int M, int B,
                                                                   float* __restrict__ out) {
-    __shared__ float tile[32][65];
-    const int b0 = blockIdx.z * 64, c0 = blockIdx.y * 32;
+    __shared__ float tile[64][65];
+    const int b0 = blockIdx.z * 64, c0 = blockIdx.y * 64;
     const size_t m = blockIdx.x;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;     // 64 x 4
-    for (int r = ty; r < 32; r += 4) {
-        const int c = c0 + r, b = b0 + tx;
-        if (c < C2 && b < B) tile[r][tx] = in[((size_t)c * M + m) * B + b];
+    const int q = threadIdx.x & 15, rr = threadIdx.x >> 4;       // 16 lanes x 4 elements per row
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int r = p * 16 + rr, c = c0 + r, b = b0 + 4 * q;
+        if (c >= C2) continue;
+        const float* src = in + ((size_t)c * M + m) * B + b;
+        if (VEC && b + 3 < B) {
+            const float4 v = *reinterpret_cast<const float4*>(src);
+            tile[r][4 * q + 0] = v.x;
+            tile[r][4 * q + 1] = v.y;
+            tile[r][4 * q + 2] = v.z;
+            tile[r][4 * q + 3] = v.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (b + e < B) tile[r][4 * q + e] = src[e];
+        }
     }
     __syncthreads();
-    const int cx = threadIdx.x & 31, by = threadIdx.x >> 5;     // 32 x 8
-    for (int r = by; r < 64; r += 8) {
-        const int b = b0 + r, c = c0 + cx;
-        if (c < C2 && b < B) out[((size_t)b * M + m) * C2 + c] = tile[cx][r];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int rb = p * 16 + rr, b = b0 + rb, c = c0 + 4 * q;
+        if (b >= B) continue;
+        float* dst = out + ((size_t)b * M + m) * C2 + c;
+        if (VEC && c + 3 < C2) {
+            float4 v;
+            v.x = tile[4 * q + 0][rb];
+            v.y = tile[4 * q + 1][rb];
+            v.z = tile[4 * q + 2][rb];
+            v.w = tile[4 * q + 3][rb];
+            *reinterpret_cast<float4*>(dst) = v;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (c + e < C2) dst[e] = tile[4 * q + e][rb];
+        }
     }
 }
 
 hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, float* out, hipStream_t st) {
-    dim3 g((unsigned)M, (unsigned)((C2 + 31) / 32), (unsigned)((B + 63) / 64)), b(256);
-    hipLaunchKernelGGL(stage_to_beam_major_kernel, g, b, 0, st, stage, C2, M, B, out);
+    dim3 g((unsigned)M, (unsigned)((C2 + 63) / 64), (unsigned)((B + 63) / 64)), b(256);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(stage) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+    if (aligned && B % 4 == 0 && C2 % 4 == 0)
+        hipLaunchKernelGGL(stage_to_beam_major_kernel<true>, g, b, 0, st, stage, C2, M, B, out);
+    else
+        hipLaunchKernelGGL(stage_to_beam_major_kernel<false>, g, b, 0, st, stage, C2, M, B, out);
     return hipGetLastError();
 }
 

@@ -88,7 +88,7 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
     // Stokes go to channel-major staging first (as in lbf_beamform), then to
     // the beam-major outputs
     char* stage = nullptr;
-    hipError_t e = hipMallocAsync((void**)&stage, stage_bytes, st);
+    hipError_t e = staging_alloc((void**)&stage, stage_bytes, st);
     if (e != hipSuccess) return e;
     for (int j = 0; j < a.n; ++j) {
         a.blk[j].out = stage + stage_off[j];

@@ -648,11 +648,15 @@ LBF_INLINE WaveTiles wave_tiles(int wave, int T, int t_int) {
 // (work items of 256 beams), else two (items of 128 beams).
 __host__ __device__ inline int fast_h_streams(const BlockDesc& d) { return d.B > 128 ? 1 : 2; }
 
-// work items of the fast FP16/BF16 worker: (channel, group of 256/NS beams)
+// Work items of the fast FP16/BF16 worker: (channel, group of 256/NS beams,
+// segment of up to kSegTiles 32-sample tiles) -- long blocks are cut in time
+// so that few-channel blocks still spread over all compute units.
+constexpr int kSegTiles = 24;
 inline int block_items_fast_h(const BlockDesc& d, int* nbg) {
     const int per = 8 / fast_h_streams(d) * kTile;
     *nbg = (d.B + per - 1) / per;
-    return d.C * *nbg;
+    const int ntiles = (d.T + kTile - 1) / kTile;
+    return d.C * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
 }
 
 // number of (channel group, beam group) work items of a block

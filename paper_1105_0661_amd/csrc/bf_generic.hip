@@ -5,6 +5,8 @@
 #include "bf_common.h"
 #include "bf_workers.h"
 
+#include <mutex>
+
 namespace lbf {
 
 template <int XT, int PR>
@@ -65,6 +67,26 @@ static hipError_t launch_fast(const BlockDesc& d, hipStream_t st) {
     return launch_fast_bf16(d, st);
 }
 
+// Staging buffers come from the device's default stream-ordered pool.  The
+// pool keeps freed memory (instead of unmapping it at every synchronisation),
+// so a block's staging costs no page mapping once the pool has grown.
+hipError_t staging_alloc(void** p, size_t bytes, hipStream_t st) {
+    static std::once_flag flags[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < 64) {
+        std::call_once(flags[dev], [dev] {
+            hipMemPool_t pool;
+            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+                uint64_t keep = ~0ull;
+                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            }
+        });
+    }
+    return hipMallocAsync(p, bytes, st);
+}
+
 // lbf_beamform: the fast workers where they apply, the generic ones otherwise.
 // The fast workers write Stokes products channel-major ([C'][K][T'][B], beams
 // fastest); a beam-major block (order 0) goes through a staging buffer of that
@@ -75,7 +97,7 @@ hipError_t launch_beamform(const BlockDesc& d, hipStream_t st) {
     const int K = d.product == PR_IQUV ? 4 : 1;
     const int T2 = d.T / d.t_int;
     void* stage = nullptr;
-    hipError_t e = hipMallocAsync(&stage, (size_t)d.C * K * T2 * d.B * sizeof(float), st);
+    hipError_t e = staging_alloc(&stage, (size_t)d.C * K * T2 * d.B * sizeof(float), st);
     if (e != hipSuccess) return e;
     BlockDesc ds = d;
     ds.out = stage;

@@ -147,13 +147,19 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     constexpr int CPS = kTile / SPC;                       // chunks per station per tile
     constexpr int CPTILE = 8 * NK * CPS;                   // chunks per tile
     constexpr int CPT = (NS * CPTILE + kThreadsH - 1) / kThreadsH;   // chunks per thread per step
-    const int c = item / nbg, bg = item % nbg;
+    // item = (channel, beam group, segment of up to kSegTiles sample tiles)
+    const int T = d.T;
+    const int ntiles_all = (T + kTile - 1) / kTile;
+    const int nseg = (ntiles_all + kSegTiles - 1) / kSegTiles;
+    const int seg = item % nseg;
+    const int c = item / nseg / nbg, bg = item / nseg % nbg;
+    const int tile_lo = seg * kSegTiles;                   // tiles [tile_lo, tile_lo + ntiles)
+    const int ntiles = min(kSegTiles, ntiles_all - tile_lo);
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int r = lane & 31, h = lane >> 5;
     const int bt = wave % NBT, sigma = wave / NBT;         // beam tile, sample stream
-    const int S = d.S, T = d.T, B = d.B;
+    const int S = d.S, B = d.B;
     const int beam = (bg * NBT + bt) * kTile + r;
-    const int ntiles = (T + kTile - 1) / kTile;
     const int nsteps = (ntiles + NS - 1) / NS;
     const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
     constexpr int K = PR == PR_IQUV ? 4 : 1;
@@ -185,7 +191,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
         for (int i = 0; i < CPT; ++i) {
             const int j = tid + kThreadsH * i;
             const int sg = j / CPTILE, jt = j % CPTILE, s = jt / CPS, q = jt % CPS;
-            const int tile = min(sg + NS * k, ntiles - 1);
+            const int tile = tile_lo + min(sg + NS * k, ntiles - 1);
             // descriptor over the whole planes of the group's stations, the
             // channel in the offset: a ragged last tile reads past the end of
             // the channel into the next one, or past the last valid station
@@ -232,8 +238,8 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
         u32x4 ax[2], ay[2];
         ax[0] = *reinterpret_cast<const u32x4*>(ax0 + 4 * (h ^ sw));
         ay[0] = *reinterpret_cast<const u32x4*>(ax0 + kARow + 4 * (h ^ sw));
-        const int tprev = sigma + NS * (k - 1);
-        const bool okprev = k >= 1 && tprev < ntiles && beam < B;
+        const int tprev = tile_lo + sigma + NS * (k - 1);
+        const bool okprev = k >= 1 && tprev < tile_lo + ntiles && beam < B;
         float sm[NOUT][4];
 #pragma unroll
         for (int o = 0; o < NOUT; ++o)
@@ -302,8 +308,8 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     };
     // the last tile's epilogue: one more step without MFMAs
     auto final_epilogue = [&](const floatx16 (&prev)[4], int klast) {
-        const int tile = sigma + NS * klast;
-        const bool ok = klast >= 0 && tile < ntiles && beam < B;
+        const int tile = tile_lo + sigma + NS * klast;
+        const bool ok = klast >= 0 && tile < tile_lo + ntiles && beam < B;
         if (PR == PR_VOLT) volt_store_cm(prev, ors, T, beam, tile * kTile, h, ok);
         else stokes_store_cm<PR, TI>(prev, ors, B, T2, beam, tile * kTile, h, ok);
     };

@@ -18,6 +18,7 @@ hipError_t launch_fast_f32(const BlockDesc& d, hipStream_t st);
 hipError_t launch_fast_f16(const BlockDesc& d, hipStream_t st);
 hipError_t launch_fast_bf16(const BlockDesc& d, hipStream_t st);
 hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, hipStream_t st);
+hipError_t staging_alloc(void** p, size_t bytes, hipStream_t st);
 hipError_t launch_stokes(const float* y, int B, int C, int T, int product, int t_int, int f_int, float* s,
                          hipStream_t st);
 hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int elem_bytes, void* out,

@@ -224,6 +224,21 @@ def test_channel_major_then_beam_major_equals_fused(ctype, S, product, t_int, f_
     _check_stokes(bm.cpu().numpy(), _oracle_stokes(blk, product, t_int, f_int), TOL[ctype], "channel-major")
 
 
+@pytest.mark.parametrize("ctype,B,xtype", [(lbf.F16, 140, "ci8"), (lbf.BF16, 50, "ci16"), (lbf.F16, 50, "ci16")],
+                         ids=["f16-B140-ci8", "bf16-B50-ci16", "f16-B50-ci16"])
+def test_long_block_is_cut_into_time_segments(ctype, B, xtype):
+    # more than 24 tiles of 32 samples: work items cover segments of the block
+    torch = _torch()
+    blk = synth.make_block(20, B, 1, 3, 1100, xtype, 16.0 if xtype == "ci8" else 40.0, tag=(1105, 661, 66))
+    flush("time segments %s B=%d T=1100" % (CT_NAMES[ctype], B))
+    x, w = to_dev(blk.x), _weights(blk, ctype)
+    out = lbf.beamform(x, w, lbf.STOKES_IQUV, 4, 1)
+    y = lbf.beamform(x, w, lbf.VOLTAGES)
+    torch.cuda.synchronize()
+    _check_stokes(out.cpu().numpy(), _oracle_stokes(blk, 4, 4, 1), TOL[ctype], "segments")
+    assert relerr(cplx(y), orc.beamform(blk.x, orc.block_weights(blk))) <= TOL[ctype]
+
+
 def test_beam_major_reorder_is_exact():
     torch = _torch()
     g = torch.Generator(device="cuda:0").manual_seed(4)
