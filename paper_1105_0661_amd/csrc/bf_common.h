@@ -23,6 +23,7 @@ constexpr int kBeamTiles = kBeamGroup / kTile;
 constexpr int kStationChunk = 64;               // stations whose weights sit in LDS at once
 constexpr int kWavesPerGroup = 4;
 constexpr int kThreads = kWave * kWavesPerGroup;
+constexpr int kThreadsH = 512;                 // fast workers: 8 waves, two per SIMD
 constexpr int kWRow = kStationChunk + 4;        // LDS row of packed f16/bf16 weights (words)
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -655,6 +656,13 @@ constexpr int kSegTiles = 24;
 inline int block_items_fast_h(const BlockDesc& d, int* nbg) {
     const int per = 8 / fast_h_streams(d) * kTile;
     *nbg = (d.B + per - 1) / per;
+    const int ntiles = (d.T + kTile - 1) / kTile;
+    return d.C * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
+}
+
+// work items of the fast FP32 worker: (channel, group of 128 beams, segment)
+inline int block_items_fast_f32(const BlockDesc& d, int* nbg) {
+    *nbg = (d.B + kBeamGroup - 1) / kBeamGroup;
     const int ntiles = (d.T + kTile - 1) / kTile;
     return d.C * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
 }

@@ -6,10 +6,11 @@
 
 namespace lbf {
 
+// 8 waves, two per SIMD; LDS: the three weight planes of 128 beams
 template <int XT, int PR, int TI>
-__global__ __launch_bounds__(kThreads) void bf_f32_fast_kernel(BlockDesc d, int nbg, int nitems) {
-    __shared__ float wl[kStationChunk * 2 * kBeamGroup];
-    item_f32_fast<XT, PR, TI>(d, xcd_remap(blockIdx.x, nitems), nbg, wl);
+__global__ __launch_bounds__(kThreadsH) void bf_f32_fast_kernel(BlockDesc d, int nbg, int nitems) {
+    __shared__ __attribute__((aligned(16))) float pl[3 * kPlaneWords];
+    item_f32_fast<XT, PR, TI>(d, xcd_remap(blockIdx.x, nitems), nbg, pl);
 }
 
 // 8 waves, two per SIMD; LDS: NS streams x 2 buffers of one A tile
@@ -22,7 +23,7 @@ __global__ __launch_bounds__(kThreadsH) void bf_h_fast_kernel(BlockDesc d, int n
 // launch one instantiation; PR/TI/NK chosen from the block by the callers
 template <int XT, int PR, int TI>
 inline hipError_t launch_f32_k(const BlockDesc& d, int nbg, int n, hipStream_t st) {
-    hipLaunchKernelGGL((bf_f32_fast_kernel<XT, PR, TI>), dim3(n), dim3(kThreads), 0, st, d, nbg, n);
+    hipLaunchKernelGGL((bf_f32_fast_kernel<XT, PR, TI>), dim3(n), dim3(kThreadsH), 0, st, d, nbg, n);
     return hipGetLastError();
 }
 

@@ -17,82 +17,198 @@ namespace lbf {
 // fast workers: up to 64 stations of complex int8/int16 samples
 // ===========================================================================
 
-// FP32 operands (MFMA 32x32x2 f32: one station per step, K = re/im).
-// Station samples stream through an 8-deep register ring so each load has
-// 8 stations' worth of MFMAs (8 x 16 x 64 cycles) to arrive.  Rows of a
-// ragged last tile read a valid sample and are never stored.
+// FP32 operands (MFMA 32x32x2 f32: one station per MFMA, K = (re, im)).
+//
+// A work item is one channel, 128 beams and a segment of up to kSegTiles
+// sample tiles; a work group has 8 waves (two per SIMD).  The weights of the
+// 128 beams sit in LDS as three planes p0 = w_re, p1 = -w_im, p2 = w_im
+// ([beam][station] rows), so that lane half h (the K index) multiplies the
+// plain sample component a = (h ? x_im : x_re) by  wr = (h ? p1 : p0)  for
+// Re y and by  wi = (h ? p0 : p2)  for Im y.  Wave w owns beam tile w % 4 and
+// every other sample tile (stream w / 4); its two accumulator sets (4 x 16
+// floats each, in VGPRs) alternate between tiles, and the Stokes epilogue of
+// the previous tile is spread between the MFMAs of the current one (a wave's
+// own VALU work overlaps its MFMAs).  Samples stream from HBM through an
+// 8-deep register ring, one group of 8 stations ahead.
+constexpr int kPlaneWords = kBeamGroup * kWRow;          // one plane: 34 KB
+
+LBF_INLINE void stage_weights_f32_planes(float* pl, const BlockDesc& d, int c, int b0) {
+    constexpr int R = kStationChunk * kBeamGroup / kThreadsH;   // 16 per thread
+    constexpr int RS = kThreadsH / kStationChunk;                // beam rows per pass
+    typedef float float2v __attribute__((ext_vector_type(2)));
+    const int sl = threadIdx.x % kStationChunk, b1 = threadIdx.x / kStationChunk;
+    const __amdgpu_buffer_rsrc_t rs = weight_rsrc(d, c, 8);
+    const bool sok = sl < d.S;
+    float2v v[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        v[k] = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(((uint32_t)(b0 + b1 + RS * k) * d.S + sl) * 8u), 0, 0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int bl = b1 + RS * k;
+        const float wre = sok ? v[k][0] : 0.f, wim = sok ? v[k][1] : 0.f;
+        pl[bl * kWRow + sl] = wre;
+        pl[kPlaneWords + bl * kWRow + sl] = -wim;
+        pl[2 * kPlaneWords + bl * kWRow + sl] = wim;
+    }
+}
+
 template <int XT, int PR, int TI>
-LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* wl) {
+LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) {
     typedef Raw<XT> R;
     typedef typename R::type RT;
     constexpr int BYTES = sizeof(RT);
-    const int g = item / nbg, bg = item % nbg;
+    constexpr int NOUT = PR == PR_VOLT ? 1 : 16 / TI;
+    constexpr int K = PR == PR_IQUV ? 4 : 1;
+    const int T = d.T, S = d.S, B = d.B;
+    const int ntiles_all = (T + kTile - 1) / kTile;
+    const int nseg = (ntiles_all + kSegTiles - 1) / kSegTiles;
+    const int seg = item % nseg;
+    const int c = item / nseg / nbg, bg = item / nseg % nbg;
+    const int tile_lo = seg * kSegTiles;
+    const int ntiles = min(kSegTiles, ntiles_all - tile_lo);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int r = lane & 31, h = lane >> 5;
-    const int S = d.S, C = d.C, T = d.T;
+    const int bt = wave & 3, ts = wave >> 2;
     const int b0 = bg * kBeamGroup;
-    const int f_int = 1;                             // fast path: no channel integration
-    EpiCtx e = make_epi(d, PR, g);
-    const WaveTiles wt = wave_tiles(wave, T, TI);
+    const int beam = b0 + bt * kTile + r;
+    const int nmine = ntiles > ts ? (ntiles - ts + 1) / 2 : 0;  // this wave's tiles
+    // groups of 8 stations, rounded up to an even count so that group n of the
+    // wave's sequence always sits in ring slot n % 2 = gi % 2 (a group past
+    // the stations reads zeros and has zero weights)
+    const int ngrp = min(8, ((S + 7) / 8 + 1) & ~1);
+    const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
+    const int T2 = PR == PR_VOLT ? T : T / TI;
+    const __amdgpu_buffer_rsrc_t ors =
+        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)K * T2 * B * 4u);
     const int trow = tile_row_sample(r);
-    const int ngrp = (S + 7) / 8;                    // groups of 8 stations
-    const uint32_t stride_bytes = (uint32_t)((size_t)C * T * BYTES);
 
-    for (int j = 0; j < f_int; ++j) {
-        const int c = g * f_int + j;
-        e.c = c;
-        e.first = j == 0;
-        __syncthreads();
-        stage_weights_f32_fast(wl, d, c, b0);
-        __syncthreads();
-        for (int k = 0; k < wt.ntw; ++k) {
-            const int t0 = wt.tile(k) * kTile;
-            const uint32_t toff = (uint32_t)min(t0 + trow, T - 1) * BYTES;
-            int widx = h * kBeamGroup + r;                // LDS reads stay in the loop
-            __asm__ volatile("" : "+v"(widx));
-            const float* wcol = wl + widx;
-            floatx16 acc[kBeamTiles][4];
-            RT ring[8];
-            __amdgpu_buffer_rsrc_t rs = station_group_rsrc(d.x, BYTES, 0, S, c, T, stride_bytes);
+    stage_weights_f32_planes(pl, d, c, b0);
+    __syncthreads();
+    if (nmine == 0 || b0 + bt * kTile >= B) return;             // nothing of this wave's (no barrier follows)
+    // LDS rows of this lane: the plane for Re y and the one for Im y
+    int wro = (h ? kPlaneWords : 0) + (bt * kTile + r) * kWRow;
+    int wio = (h ? 0 : 2 * kPlaneWords) + (bt * kTile + r) * kWRow;
+    __asm__ volatile("" : "+v"(wro), "+v"(wio));
+
+    auto tile_of = [&](int k) { return tile_lo + ts + 2 * k; };
+    // Two-deep ring of 8-station groups: group n of the wave's sequence
+    // (tile n / ngrp, group n % ngrp) lands in slot n % 2 two groups before
+    // it is used, which covers a cache-missing load.
+    RT ring[2][8];
+    auto load_quad = [&](int slot, int q4, int n) {            // stations 4 q4 .. 4 q4 + 3 of group n
+        const int k = min(n / ngrp, nmine - 1), g = n % ngrp;
+        const int t = min(tile_of(k) * kTile + trow, T - 1);
+        const __amdgpu_buffer_rsrc_t rs = station_group_rsrc(d.x, BYTES, 8 * g, S, c, T, stride_bytes);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) ring[i] = buffer_sample<XT>(rs, toff + (uint32_t)i * stride_bytes);
-            // one group of 8 stations; the very first station starts the
-            // accumulators from zero (peeled so the choice is compile-time)
-            auto group8 = [&](int gi, auto first_tag) {
-                constexpr bool FIRST = decltype(first_tag)::value;
-                const __amdgpu_buffer_rsrc_t rn = station_group_rsrc(d.x, BYTES, 8 * gi + 8, S, c, T, stride_bytes);
+        for (int i = 4 * q4; i < 4 * q4 + 4; ++i)
+            ring[slot][i] = buffer_sample<XT>(rs, (uint32_t)t * BYTES + (uint32_t)i * stride_bytes);
+    };
+    auto epi_sample = [&](const floatx16 (&prev)[4], int tprev, bool okprev, int smp, float (&sm)[NOUT][4]) {
+        if (PR == PR_VOLT) {
+            const int t = tprev * kTile + 16 * h + smp;
+            const uint32_t off = store_off(okprev && beam < B && t < T, ((uint32_t)beam * T + t) * 16u);
+            floatx4 vv;
+            vv[0] = prev[0][smp];
+            vv[1] = prev[1][smp];
+            vv[2] = prev[2][smp];
+            vv[3] = prev[3][smp];
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, vv), ors, (int)off, 0, 0);
+        } else {
+            stokes_add<PR>(prev, smp, sm[smp / TI]);
+        }
+    };
+
+    // one tile: MFMAs into acc, with the epilogue of prev (tile k-1) spread
+    // over the station groups (two of its 16 samples per group)
+    auto step = [&](int k, floatx16 (&acc)[4], const floatx16 (&prev)[4]) {
+        const int tprev = tile_of(k - 1);
+        const bool okprev = k >= 1;
+        float sm[NOUT][4];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int s = gi * 8 + i;
-                    const floatx4 v = R::cvt(ring[i]);
-                    ring[i] = buffer_sample<XT>(rn, toff + (uint32_t)i * stride_bytes);
-                    const float aXr = h ? -v[1] : v[0];
-                    const float aXi = h ? v[0] : v[1];
-                    const float aYr = h ? -v[3] : v[2];
-                    const float aYi = h ? v[2] : v[3];
-                    float bw[kBeamTiles];
+        for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-                    for (int a = 0; a < kBeamTiles; ++a) bw[a] = wcol[s * 2 * kBeamGroup + a * kTile];
+            for (int q = 0; q < 4; ++q) sm[o][q] = 0.f;
 #pragma unroll
-                    for (int a = 0; a < kBeamTiles; ++a) {
-                        if (FIRST && i == 0) {
-                            acc[a][0] = mfma_f32(aXr, bw[a], zero16());
-                            acc[a][1] = mfma_f32(aXi, bw[a], zero16());
-                            acc[a][2] = mfma_f32(aYr, bw[a], zero16());
-                            acc[a][3] = mfma_f32(aYi, bw[a], zero16());
-                        } else {
-                            acc[a][0] = mfma_f32(aXr, bw[a], acc[a][0]);
-                            acc[a][1] = mfma_f32(aXi, bw[a], acc[a][1]);
-                            acc[a][2] = mfma_f32(aYr, bw[a], acc[a][2]);
-                            acc[a][3] = mfma_f32(aYi, bw[a], acc[a][3]);
-                        }
+        for (int gi = 0; gi < 8; ++gi) {
+            if (gi < ngrp) {                                   // uniform
+                // group n = k ngrp + gi sits in slot gi % 2; as soon as a quad
+                // of its stations is converted, the same registers are
+                // refilled with that quad of group n + 2
+#pragma unroll
+                for (int i4 = 0; i4 < 2; ++i4) {               // 4 stations at a time
+                    const int s4 = 8 * gi + 4 * i4;
+                    float ax[4], ay[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const floatx4 v = R::cvt(ring[gi & 1][4 * i4 + i]);
+                        ax[i] = h ? v[1] : v[0];
+                        ay[i] = h ? v[3] : v[2];
+                    }
+                    load_quad(gi & 1, i4, k * ngrp + gi + 2);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const floatx4 br = *reinterpret_cast<const floatx4*>(pl + wro + s4);
+                    const floatx4 bi = *reinterpret_cast<const floatx4*>(pl + wio + s4);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const bool first = gi == 0 && i4 == 0 && i == 0;
+                        acc[0] = mfma_f32(ax[i], br[i], first ? zero16() : acc[0]);
+                        acc[1] = mfma_f32(ax[i], bi[i], first ? zero16() : acc[1]);
+                        acc[2] = mfma_f32(ay[i], br[i], first ? zero16() : acc[2]);
+                        acc[3] = mfma_f32(ay[i], bi[i], first ? zero16() : acc[3]);
                     }
                 }
-            };
-            group8(0, std::true_type{});
-            for (int gi = 1; gi < ngrp; ++gi) group8(gi, std::false_type{});
-            epilogue_tiles_fixed<PR, TI>(acc, e, b0, r, t0, h);
+            }
+            epi_sample(prev, tprev, okprev, 2 * gi, sm);
+            epi_sample(prev, tprev, okprev, 2 * gi + 1, sm);
+            if (PR != PR_VOLT) {
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) __asm__ volatile("" : "+v"(sm[o][q]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
+        if (PR != PR_VOLT) {
+            const int tq0 = (tprev * kTile + 16 * h) / TI;
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) {
+                float v[4];
+                stokes_from_sums<PR>(sm[o], v);
+                const int tq = tq0 + o;
+#pragma unroll
+                for (int kq = 0; kq < K; ++kq) {
+                    const uint32_t off =
+                        store_off(okprev && beam < B && tq < T2, (((uint32_t)kq * T2 + tq) * (uint32_t)B + beam) * 4u);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[kq]), ors, (int)off, 0, 0);
+                }
+            }
+        }
+    };
+    auto final_epilogue = [&](const floatx16 (&prev)[4], int klast) {
+        const int tile = tile_of(klast);
+        const bool ok = klast >= 0 && beam < B;
+        if (PR == PR_VOLT) volt_store_cm(prev, ors, T, beam, tile * kTile, h, ok);
+        else stokes_store_cm<PR, TI>(prev, ors, B, T2, beam, tile * kTile, h, ok);
+    };
+
+    load_quad(0, 0, 0);
+    load_quad(0, 1, 0);
+    load_quad(1, 0, 1);
+    load_quad(1, 1, 1);
+    floatx16 acc0[4], acc1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc1[q] = zero16();
+    int k = 0;
+    for (; k + 1 < nmine; k += 2) {
+        step(k, acc0, acc1);
+        step(k + 1, acc1, acc0);
+    }
+    if (k < nmine) {
+        step(k, acc0, acc1);
+        final_epilogue(acc0, k);
+    } else {
+        final_epilogue(acc1, k - 1);
     }
 }
 
@@ -109,7 +225,6 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* wl) 
 // barrier per step) for all beam tiles to read.  Waves 4-7 defer each tile's
 // Stokes epilogue to the next step, so on every SIMD one wave's epilogue
 // (VALU) runs while the other wave's MFMAs do.
-constexpr int kThreadsH = 512;
 constexpr int kARow = 68;                          // words per (sample, polarisation) row of an A tile
 constexpr int kATileWords = kTile * 2 * kARow;     // 17 KB
 
