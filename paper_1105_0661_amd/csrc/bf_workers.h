@@ -301,7 +301,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     // loaders: chunk j = tid + 512 i of a step covers stream j / CPTILE,
     // station (j % CPTILE) / CPS and samples SPC * (j % CPS) + [0, SPC)
     u32x4 raw[CPT];
-    auto load_chunks = [&](int k) {
+    auto load_chunks_to = [&](int k, u32x4 (&dst)[CPT]) {
 #pragma unroll
         for (int i = 0; i < CPT; ++i) {
             const int j = tid + kThreadsH * i;
@@ -313,10 +313,11 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
             // (out of range: zeros), never past the array
             const __amdgpu_buffer_rsrc_t rs = station_group_rsrc(d.x, BYTES, s & ~7, S, 0, T, stride_bytes);
             const uint32_t off = (uint32_t)(s & 7) * stride_bytes + (uint32_t)(c * T + tile * kTile + q * SPC) * BYTES;
-            raw[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+            dst[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
         }
     };
-    auto store_chunk = [&](int k, int i) {
+    auto load_chunks = [&](int k) { load_chunks_to(k, raw); };
+    auto store_chunk_from = [&](int k, int i, const u32x4 (&src)[CPT]) {
         const int j = tid + kThreadsH * i;
         const int sg = j / CPTILE, jt = j % CPTILE, s = jt / CPS, q = jt % CPS;
         if (NS * CPTILE % kThreadsH == 0 || j < NS * CPTILE) {
@@ -324,13 +325,14 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
 #pragma unroll
             for (int js = 0; js < SPC; ++js) {
                 uint32_t fx, fy;
-                Chunk<XT, CT>::xy(raw[i], js, fx, fy);
+                Chunk<XT, CT>::xy(src[i], js, fx, fy);
                 const int t = q * SPC + js;
                 ab[a_word(t, 0, s)] = fx;
                 ab[a_word(t, 1, s)] = fy;
             }
         }
     };
+    auto store_chunk = [&](int k, int i) { store_chunk_from(k, i, raw); };
 
     // One step k, written out in the order it should run: K-step kk's four
     // MFMAs (operands read one K-step ahead from LDS), then 1/NK of the
@@ -435,10 +437,13 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     __syncthreads();
     if (!PIPE) {
         // one accumulator set (complex int16 with two streams: the loaders'
-        // registers leave no room for a second): MFMAs, then the epilogue
+        // registers leave no room for a second): MFMAs, then the epilogue.
+        // The samples of step j sit in rr[j % 2], loaded two steps ahead.
         floatx16 acc[4];
-        for (int k = 0; k < nsteps; ++k) {
-            load_chunks(k + 1);
+        u32x4 rr[2][CPT];
+        load_chunks_to(1, rr[1]);
+        auto plain_step = [&](int k, u32x4 (&mine)[CPT], u32x4 (&next)[CPT]) {
+            load_chunks_to(k + 2, mine);                       // mine held step k's samples, now in LDS
             int rowx = (sigma * 2 + (k & 1)) * kATileWords + 2 * trow * kARow;
             __asm__ volatile("" : "+v"(rowx));
             const uint32_t* ax0 = at + rowx;
@@ -455,9 +460,15 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
             }
             final_epilogue(acc, k);
 #pragma unroll
-            for (int i = 0; i < CPT; ++i) store_chunk(k + 1, i);
+            for (int i = 0; i < CPT; ++i) store_chunk_from(k + 1, i, next);
             __syncthreads();
+        };
+        int k = 0;
+        for (; k + 1 < nsteps; k += 2) {
+            plain_step(k, rr[0], rr[1]);
+            plain_step(k + 1, rr[1], rr[0]);
         }
+        if (k < nsteps) plain_step(k, rr[0], rr[1]);
         return;
     }
     floatx16 acc0[4], acc1[4];
