@@ -209,6 +209,25 @@ typedef struct {
                                  0: x is device memory valid until the job is DONE  */
     int ctype, product, t_int, f_int;
     void* d_out;              /* caller-owned device output, layout as lbf_beamform  */
+    uint64_t stream_id;       /* 0: an independent block.  Otherwise the blocks of one
+                                 stream are consecutive in time and are run in
+                                 submission order; integration periods may span
+                                 blocks (T % t_int need not be 0): the samples of an
+                                 incomplete period at the end of a block stay on the
+                                 device and are prepended to the stream's next
+                                 block, so d_out receives the periods completed in
+                                 this block, [B][K][P][C'] with
+                                 P = (carried + T) / t_int (lbf_job_status.periods);
+                                 the result equals lbf_beamform on the stream's
+                                 samples concatenated in time.  Stokes products,
+                                 device-resident x only; S, C, xtype and t_int
+                                 stay those of the stream.  Arena use: a tail of
+                                 S*C*(t_int-1) samples while samples are carried,
+                                 and, for a block that carries in or out, its
+                                 S*C*P*t_int samples concatenated for the kernel.
+                                 A stream that ends on a period boundary releases
+                                 its tail and its id; a failed block fails every
+                                 later block of its stream (use a new id).        */
 } lbf_job;
 
 typedef enum { LBF_JOB_QUEUED = 0, LBF_JOB_ADMITTED = 1, LBF_JOB_RUNNING = 2, LBF_JOB_DONE = 3,
@@ -219,14 +238,17 @@ typedef struct {
     int error;                /* lbf_status of a FAILED job                            */
     uint64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns;  /* steady clock, ns       */
     int batch_size;           /* jobs in the launch that ran this job                  */
+    int periods;              /* integration periods written to d_out (T' of the block) */
 } lbf_job_status;
 
 /* Errors: LBF_E_INVAL for a malformed cfg; LBF_E_HIP if the device or streams
  * cannot be set up. */
 int lbf_server_create(const lbf_server_cfg* cfg, lbf_server** out);
 
-/* Non-blocking.  LBF_E_INVAL for a malformed job, LBF_E_NOMEM if its footprint
- * can never fit the arena, LBF_E_BUSY if the host queue is full. */
+/* Non-blocking.  LBF_E_INVAL for a malformed job (or a stream block whose S, C,
+ * xtype or t_int differ from its stream's), LBF_E_NOMEM if its footprint can
+ * never fit the arena, LBF_E_BUSY if the host queue is full, LBF_E_HIP for a
+ * block of a stream an earlier block of which failed. */
 int lbf_server_submit(lbf_server* srv, const lbf_job* job, uint64_t* ticket);
 
 /* LBF_E_NOTFOUND for an unknown ticket.  A DONE/FAILED ticket stays

@@ -9,6 +9,9 @@
 // while others run overlap on the device.  Weights stay cached on the device
 // per observation id and are evicted least-recently-used when the arena is
 // short.  Completion is observed through HIP events by the scheduler thread.
+// Blocks of one stream (stream_id != 0) run in order; the samples of an
+// integration period left incomplete at the end of a block stay in a per-stream
+// tail buffer in the arena and are prepended to the stream's next block.
 // (Section 4.1: the station stream is cut into short blocks; Section 7:
 // independent observations run in parallel while resources allow; Section 4.7:
 // a bounded buffer that refuses work rather than stalling the pipeline.)
@@ -88,6 +91,8 @@ class Arena {
 };
 
 int bytes_per_complex(int xt) { return xt == LBF_CI8 ? 2 : xt == LBF_CI16 ? 4 : 8; }
+// bytes of one time sample of one station and channel: the X and Y polarisations
+int sample_bytes(int xt) { return 2 * bytes_per_complex(xt); }
 int weight_bytes(int ct) { return ct == LBF_F32 ? 8 : 4; }
 
 struct WeightEntry {
@@ -109,6 +114,26 @@ struct JobRec {
     bool staged = false;
     uint64_t wkey = 0;
     bool new_weights = false;
+    // stream blocks: samples carried in from the tail, left in it afterwards,
+    // and run now (carry_in + T - carry_out, a whole number of periods)
+    int carry_in = 0, carry_out = 0, t_eff = 0;
+    uint64_t cat_off = 0, cat_bytes = 0;   // [S][C][t_eff]: carried samples, then x
+    bool has_cat = false;
+    struct StreamState* ss = nullptr;
+};
+
+// A stream's tail: the samples [S][C][carried] of its incomplete integration
+// period, pitch t_int - 1 samples.  Host bookkeeping (carried, pending) follows
+// admission order; the device copies that read and write the tail are ordered
+// by `ev`, recorded after each block's copies.
+struct StreamState {
+    int S = 0, C = 0, xtype = 0, t_int = 0;
+    int carried = 0;              // samples in the tail after the last admitted block
+    int pending = 0;              // admitted blocks not yet done
+    bool broken = false;          // a block failed: later blocks fail too
+    uint64_t tail_off = 0, tail_bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool ev_valid = false;
 };
 
 struct Launch {
@@ -128,6 +153,7 @@ struct lbf_server {
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, std::unique_ptr<JobRec>> jobs;
     std::map<uint64_t, WeightEntry> wcache;   // key: obs_id * 4 + ctype
+    std::unordered_map<uint64_t, StreamState> sstate;
     std::vector<Launch> inflight;
     int inflight_jobs = 0;
     Arena arena;
@@ -151,11 +177,13 @@ int validate_job(const lbf_job* j) {
     if (j->product != LBF_VOLTAGES && j->product != LBF_STOKES_I && j->product != LBF_STOKES_IQUV)
         return set_error(LBF_E_INVAL, "lbf_server_submit: unknown product");
     if (j->t_int < 1 || j->f_int < 1) return set_error(LBF_E_INVAL, "lbf_server_submit: t_int, f_int must be >= 1");
+    if (j->stream_id != 0 && (j->product == LBF_VOLTAGES || j->x_on_host))
+        return set_error(LBF_E_INVAL, "lbf_server_submit: stream blocks take Stokes products of device samples");
     if (j->product == LBF_VOLTAGES) {
         if (j->t_int != 1 || j->f_int != 1)
             return set_error(LBF_E_INVAL, "lbf_server_submit: voltages take t_int = f_int = 1");
     } else {
-        if (j->T % j->t_int || j->C % j->f_int)
+        if ((j->stream_id == 0 && j->T % j->t_int) || j->C % j->f_int)
             return set_error(LBF_E_INVAL, "lbf_server_submit: t_int must divide T and f_int must divide C");
         if (j->t_int & (j->t_int - 1))
             return set_error(LBF_E_UNSUPPORTED, "lbf_server_submit: t_int must be a power of two");
@@ -169,36 +197,85 @@ uint64_t weights_alloc_bytes(const lbf_job& j) {
 }
 
 uint64_t staging_bytes(const lbf_job& j) {
-    return j.x_on_host ? (uint64_t)j.S * j.C * j.T * 2 * bytes_per_complex(j.xtype) : 0;
+    return j.x_on_host ? (uint64_t)j.S * j.C * j.T * sample_bytes(j.xtype) : 0;
+}
+
+// samples [S][C][n] of a stream block
+uint64_t stream_bytes(const lbf_job& j, int n) { return (uint64_t)j.S * j.C * n * sample_bytes(j.xtype); }
+
+// the most a stream block can ever hold in the arena besides weights
+uint64_t stream_max_bytes(const lbf_job& j) {
+    if (!j.stream_id) return 0;
+    return align_up(stream_bytes(j, j.T + j.t_int - 1)) + align_up(stream_bytes(j, j.t_int - 1));
 }
 
 char* arena_ptr(lbf_server* s, uint64_t off) { return (char*)s->cfg.d_arena + off; }
 
-// Try to place a job's device state.  Called with the lock held.
-bool try_admit(lbf_server* s, JobRec* r) {
+enum { kAdmitWait = 0, kAdmitted = 1, kAdmitReject = 2 };
+
+// Give a stream's tail back to the arena (no block of it may be pending).
+void drop_tail(lbf_server* s, StreamState* ss) {
+    if (ss->tail_bytes) s->arena.release(ss->tail_off, ss->tail_bytes);
+    ss->tail_bytes = 0;
+    if (ss->ev) (void)hipEventDestroy(ss->ev);
+    ss->ev = nullptr;
+    ss->ev_valid = false;
+}
+
+bool stream_shape_differs(const StreamState& ss, const lbf_job& j) {
+    return ss.S != j.S || ss.C != j.C || ss.xtype != j.xtype || ss.t_int != j.t_int;
+}
+
+// Try to place a job's device state.  Called with the lock held.  Returns
+// kAdmitWait when it must wait for memory (or for an in-use weight set), and
+// kAdmitReject (with r->st.error set) when it can never run.
+int try_admit(lbf_server* s, JobRec* r) {
     const lbf_job& j = r->job;
+    // stream blocks: what is carried in, run, and carried out
+    int cin = 0, cout = 0, teff = j.T;
+    uint64_t need_cat = 0, need_tail = 0;
+    StreamState* ss = nullptr;
+    if (j.stream_id) {
+        auto f = s->sstate.find(j.stream_id);
+        if (f != s->sstate.end()) {
+            ss = &f->second;
+            if (ss->broken) {
+                r->st.error = LBF_E_HIP;
+                return kAdmitReject;
+            }
+            if (stream_shape_differs(*ss, j)) {   // the carried samples cannot continue: end the stream
+                ss->broken = true;
+                if (ss->pending == 0) drop_tail(s, ss);
+                r->st.error = LBF_E_INVAL;
+                return kAdmitReject;
+            }
+            cin = ss->carried;
+        }
+        cout = (cin + j.T) % j.t_int;
+        teff = cin + j.T - cout;
+        if (teff > 0 && (cin > 0 || cout > 0)) need_cat = stream_bytes(j, teff);
+        if (cout > 0 && (!ss || ss->tail_bytes == 0)) need_tail = stream_bytes(j, j.t_int - 1);
+    }
     const uint64_t key = j.obs_id * 4 + (uint64_t)j.ctype;
     auto it = s->wcache.find(key);
     bool hit = it != s->wcache.end() && it->second.S == j.S && it->second.B == j.B && it->second.C == j.C;
-    if (it != s->wcache.end() && !hit && it->second.refs > 0) return false;   // same id, other shape, in use
-    const uint64_t need_w = hit ? 0 : weights_alloc_bytes(j);
-    const uint64_t need_x = staging_bytes(j);
-    uint64_t woff = 0, xoff = 0;
+    if (it != s->wcache.end() && !hit && it->second.refs > 0) return kAdmitWait;   // same id, other shape, in use
+    const uint64_t need[4] = {hit ? 0 : weights_alloc_bytes(j), staging_bytes(j), need_cat, need_tail};
+    uint64_t off[4] = {0, 0, 0, 0};
     for (;;) {
-        bool okw = need_w == 0 || s->arena.alloc(need_w, &woff);
-        bool okx = true;
-        if (okw && need_x) {
-            okx = s->arena.alloc(need_x, &xoff);
-            if (!okx && need_w) s->arena.release(woff, need_w);
-        }
-        if (okw && okx) break;
+        int k = 0;
+        for (; k < 4; ++k)
+            if (need[k] && !s->arena.alloc(need[k], &off[k])) break;
+        if (k == 4) break;
+        for (int i = 0; i < k; ++i)
+            if (need[i]) s->arena.release(off[i], need[i]);
         // evict the least recently used idle weight set (never the one we need)
         auto victim = s->wcache.end();
         for (auto w = s->wcache.begin(); w != s->wcache.end(); ++w)
             if (w->second.refs == 0 && w->first != key &&
                 (victim == s->wcache.end() || w->second.last_use < victim->second.last_use))
                 victim = w;
-        if (victim == s->wcache.end()) return false;
+        if (victim == s->wcache.end()) return kAdmitWait;
         (void)hipEventDestroy(victim->second.ready);
         s->arena.release(victim->second.off, victim->second.bytes);
         s->wcache.erase(victim);
@@ -210,8 +287,8 @@ bool try_admit(lbf_server* s, JobRec* r) {
             s->wcache.erase(it);
         }
         WeightEntry e;
-        e.off = woff;
-        e.bytes = need_w;
+        e.off = off[0];
+        e.bytes = need[0];
         e.S = j.S; e.B = j.B; e.C = j.C; e.ctype = j.ctype;
         (void)hipEventCreateWithFlags(&e.ready, hipEventDisableTiming);
         s->wcache[key] = e;
@@ -221,30 +298,98 @@ bool try_admit(lbf_server* s, JobRec* r) {
     e.refs++;
     e.last_use = ++s->use_clock;
     r->wkey = key;
-    if (need_x) {
-        r->x_off = xoff;
-        r->x_bytes = need_x;
+    if (need[1]) {
+        r->x_off = off[1];
+        r->x_bytes = need[1];
         r->staged = true;
     }
-    return true;
+    if (j.stream_id) {
+        if (!ss) {
+            ss = &s->sstate[j.stream_id];
+            ss->S = j.S; ss->C = j.C; ss->xtype = j.xtype; ss->t_int = j.t_int;
+        }
+        if (need_tail) {
+            ss->tail_off = off[3];
+            ss->tail_bytes = need_tail;
+        }
+        ss->carried = cout;
+        ss->pending++;
+        r->ss = ss;
+        r->carry_in = cin;
+        r->carry_out = cout;
+        if (need_cat) {
+            r->cat_off = off[2];
+            r->cat_bytes = need_cat;
+            r->has_cat = true;
+        }
+    }
+    r->t_eff = teff;
+    r->st.periods = teff / j.t_int;
+    return kAdmitted;
 }
 
-void release_job(lbf_server* s, JobRec* r) {
+// Give back a finished (or failed) job's arena memory; a stream whose last
+// admitted block is done and that carries nothing gives back its tail too.
+void release_job(lbf_server* s, JobRec* r, bool failed) {
     if (r->staged) {
         s->arena.release(r->x_off, r->x_bytes);
         r->staged = false;
     }
+    if (r->has_cat) {
+        s->arena.release(r->cat_off, r->cat_bytes);
+        r->has_cat = false;
+    }
+    if (StreamState* ss = r->ss) {
+        r->ss = nullptr;
+        if (failed) ss->broken = true;
+        if (--ss->pending == 0 && (ss->carried == 0 || ss->broken)) {
+            drop_tail(s, ss);
+            if (!ss->broken) s->sstate.erase(r->job.stream_id);
+        }
+    }
     auto it = s->wcache.find(r->wkey);
     if (it != s->wcache.end() && it->second.refs > 0) it->second.refs--;
+}
+
+// Device copies of a stream block, ordered after the previous block's: the
+// carried samples and the first teff - carry_in samples of x into the
+// concatenation, then the last carry_out samples of x into the tail (or, when
+// no period completes, all of x appended to the tail).
+int stream_copies(lbf_server* s, JobRec* r, hipStream_t st) {
+    const lbf_job& j = r->job;
+    StreamState* ss = r->ss;
+    if (!ss->ev && hipEventCreateWithFlags(&ss->ev, hipEventDisableTiming) != hipSuccess) return LBF_E_HIP;
+    if (ss->ev_valid && hipStreamWaitEvent(st, ss->ev, 0) != hipSuccess) return LBF_E_HIP;
+    const size_t bpc = sample_bytes(j.xtype), rows = (size_t)j.S * j.C;
+    const size_t xp = (size_t)j.T * bpc, tp = (size_t)(j.t_int - 1) * bpc;
+    const char* x = (const char*)j.x;
+    char* tail = ss->tail_bytes ? arena_ptr(s, ss->tail_off) : nullptr;
+    const int cin = r->carry_in, cout = r->carry_out, teff = r->t_eff;
+    auto copy2d = [&](void* dst, size_t dp, const void* src, size_t sp, size_t w) {
+        return w == 0 || hipMemcpy2DAsync(dst, dp, src, sp, w, rows, hipMemcpyDeviceToDevice, st) == hipSuccess;
+    };
+    bool ok = true;
+    if (teff == 0) {
+        ok = copy2d(tail + cin * bpc, tp, x, xp, xp);
+    } else if (r->has_cat) {
+        char* cat = arena_ptr(s, r->cat_off);
+        const size_t cp = (size_t)teff * bpc;
+        ok = copy2d(cat, cp, tail, tp, cin * bpc) &&
+             copy2d(cat + cin * bpc, cp, x, xp, (size_t)(teff - cin) * bpc) &&
+             copy2d(tail, tp, x + (size_t)(j.T - cout) * bpc, xp, cout * bpc);
+    }
+    if (!ok || hipEventRecord(ss->ev, st) != hipSuccess) return LBF_E_HIP;
+    ss->ev_valid = true;
+    return LBF_OK;
 }
 
 lbf_block block_of(lbf_server* s, JobRec* r) {
     const lbf_job& j = r->job;
     const WeightEntry& e = s->wcache[r->wkey];
     lbf_block b;
-    b.d_x = r->staged ? (const void*)arena_ptr(s, r->x_off) : j.x;
+    b.d_x = r->staged ? (const void*)arena_ptr(s, r->x_off) : r->has_cat ? (const void*)arena_ptr(s, r->cat_off) : j.x;
     b.xtype = j.xtype;
-    b.S = j.S; b.C = j.C; b.T = j.T;
+    b.S = j.S; b.C = j.C; b.T = r->t_eff;
     b.d_w = arena_ptr(s, e.off);
     b.ctype = j.ctype;
     b.B = j.B;
@@ -286,7 +431,12 @@ int issue(lbf_server* s, const std::vector<JobRec*>& rs, const std::vector<lbf_b
             if (hipMemcpyAsync(arena_ptr(s, r->x_off), j.x, r->x_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
                 return LBF_E_HIP;
         }
+        if (r->ss) {
+            int rc = stream_copies(s, r, st);
+            if (rc) return rc;
+        }
     }
+    if (blocks.empty()) return LBF_OK;
     bool fused = blocks.size() > 1;
     for (const lbf_block& b : blocks)
         if (b.product == LBF_VOLTAGES || b.ctype == LBF_F32 || b.ctype != blocks[0].ctype) fused = false;
@@ -315,7 +465,7 @@ void scheduler(lbf_server* s) {
                 r->st.state = q == hipSuccess ? LBF_JOB_DONE : LBF_JOB_FAILED;
                 r->st.error = q == hipSuccess ? LBF_OK : LBF_E_HIP;
                 r->st.t_done_ns = t;
-                release_job(s, r);
+                release_job(s, r, q != hipSuccess);
                 s->inflight_jobs--;
             }
             (void)hipEventDestroy(L.done);
@@ -330,7 +480,15 @@ void scheduler(lbf_server* s) {
             auto it = s->jobs.find(s->queue.front());
             if (it == s->jobs.end()) { s->queue.pop_front(); continue; }
             JobRec* r = it->second.get();
-            if (!try_admit(s, r)) break;
+            const int a = try_admit(s, r);
+            if (a == kAdmitWait) break;
+            if (a == kAdmitReject) {   // a broken stream, or a block whose shape is not its stream's
+                r->st.state = LBF_JOB_FAILED;
+                r->st.t_done_ns = now_ns();
+                s->queue.pop_front();
+                s->cv_done.notify_all();
+                continue;
+            }
             r->st.state = LBF_JOB_ADMITTED;
             r->st.t_admit_ns = now_ns();
             s->queue.pop_front();
@@ -342,7 +500,7 @@ void scheduler(lbf_server* s) {
             std::vector<lbf_block> blocks;
             std::vector<WeightEntry> went;
             for (JobRec* r : batch) {
-                blocks.push_back(block_of(s, r));
+                if (r->t_eff > 0) blocks.push_back(block_of(s, r));   // a stream block may complete no period
                 went.push_back(s->wcache[r->wkey]);
             }
             const int si = s->next_stream;
@@ -366,7 +524,7 @@ void scheduler(lbf_server* s) {
                     r->st.state = LBF_JOB_FAILED;
                     r->st.error = rc;
                     r->st.t_done_ns = now_ns();
-                    release_job(s, r);
+                    release_job(s, r, true);
                     s->inflight_jobs--;
                 }
                 // weights this batch was to compute are not valid: drop them
@@ -436,7 +594,7 @@ int lbf_server_submit(lbf_server* s, const lbf_job* job, uint64_t* ticket) {
     if (!s || !ticket) return set_error(LBF_E_INVAL, "lbf_server_submit: NULL argument");
     int rc = validate_job(job);
     if (rc) return rc;
-    if (weights_alloc_bytes(*job) + staging_bytes(*job) > s->cfg.arena_bytes)
+    if (weights_alloc_bytes(*job) + align_up(staging_bytes(*job)) + stream_max_bytes(*job) > s->cfg.arena_bytes)
         return set_error(LBF_E_NOMEM, "lbf_server_submit: job footprint exceeds the arena");
     std::unique_ptr<JobRec> r(new JobRec());
     r->job = *job;
@@ -457,6 +615,13 @@ int lbf_server_submit(lbf_server* s, const lbf_job* job, uint64_t* ticket) {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return set_error(LBF_E_INVAL, "lbf_server_submit: server is shutting down");
     if ((int)s->queue.size() >= s->cfg.queue_capacity) return set_error(LBF_E_BUSY, "lbf_server_submit: queue full");
+    if (job->stream_id) {
+        auto f = s->sstate.find(job->stream_id);
+        if (f != s->sstate.end() && f->second.broken)
+            return set_error(LBF_E_HIP, "lbf_server_submit: an earlier block of this stream failed");
+        if (f != s->sstate.end() && stream_shape_differs(f->second, *job))
+            return set_error(LBF_E_INVAL, "lbf_server_submit: S, C, xtype and t_int must stay those of the stream");
+    }
     const uint64_t t = s->next_ticket++;
     r->ticket = t;
     s->jobs[t] = std::move(r);
@@ -516,6 +681,8 @@ int lbf_server_destroy(lbf_server* s) {
     }
     if (s->worker.joinable()) s->worker.join();
     for (auto& kv : s->wcache) (void)hipEventDestroy(kv.second.ready);
+    for (auto& kv : s->sstate)
+        if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
     for (hipStream_t st : s->streams) {
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);

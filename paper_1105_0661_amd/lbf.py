@@ -64,13 +64,13 @@ class Job(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("xtype", ctypes.c_int), ("T", ctypes.c_int),
                 ("x_on_host", ctypes.c_int),
                 ("ctype", ctypes.c_int), ("product", ctypes.c_int), ("t_int", ctypes.c_int), ("f_int", ctypes.c_int),
-                ("d_out", ctypes.c_void_p)]
+                ("d_out", ctypes.c_void_p), ("stream_id", ctypes.c_uint64)]
 
 
 class JobStatus(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int), ("error", ctypes.c_int), ("t_submit_ns", ctypes.c_uint64),
                 ("t_admit_ns", ctypes.c_uint64), ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
-                ("batch_size", ctypes.c_int)]
+                ("batch_size", ctypes.c_int), ("periods", ctypes.c_int)]
 
 
 _lock = threading.Lock()
@@ -341,9 +341,16 @@ class Server:
         _check(lib().lbf_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self._keep = {}
+        self._carry = {}     # stream_id -> samples the server carries into the stream's next block
+        self._periods = {}   # ticket -> periods its output holds
 
     def submit(self, obs_id: int, station_xyz, beam_dir, freq_hz, x, ctype: int, product: int, t_int: int = 1,
-               f_int: int = 1, out=None, ref_dir=None) -> int:
+               f_int: int = 1, out=None, ref_dir=None, stream_id: int = 0) -> int:
+        """Queue one block.  With a non-zero ``stream_id`` the block continues
+        that stream in time and its output holds (carried + T) // t_int
+        periods, carried being the samples left over from the stream's earlier
+        blocks (the same count the server keeps: the stream's total so far
+        modulo t_int)."""
         import numpy as np
         torch = _torch()
         pos = np.ascontiguousarray(station_xyz, dtype=np.float64)
@@ -360,20 +367,32 @@ class Server:
         if pos.shape != (S, 3) or dirs.shape != (B, 3) or freq.shape != (C,):
             raise ValueError("geometry shapes %s %s %s do not match samples [S=%d][C=%d]"
                              % (pos.shape, dirs.shape, freq.shape, S, C))
+        carried = self._carry.get(stream_id, 0) if stream_id else 0
+        Tq = (carried + T) // t_int * t_int if stream_id else T
         if out is None:
-            out = torch.empty(output_shape(product, S, C, T, B, t_int, f_int), dtype=torch.float32,
+            # a block that completes no period still gets a one-period buffer (never written)
+            out = torch.empty(output_shape(product, S, C, max(Tq, t_int), B, t_int, f_int), dtype=torch.float32,
                               device=self.arena.device)
         job = Job(obs_id=obs_id, station_xyz=pos.ctypes.data, S=S, beam_dir=dirs.ctypes.data, B=B,
                   ref_dir=ctypes.addressof(ref) if ref is not None else None,
                   freq_hz=freq.ctypes.data, C=C, x=x.data_ptr(), xtype=xtype_of(x), T=T, x_on_host=int(on_host),
-                  ctype=ctype, product=product, t_int=t_int, f_int=f_int, d_out=_dev_ptr(out, "out"))
+                  ctype=ctype, product=product, t_int=t_int, f_int=f_int, d_out=_dev_ptr(out, "out"),
+                  stream_id=stream_id)
         t = ctypes.c_uint64()
         _check(lib().lbf_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)))
         self._keep[t.value] = (x, out)
+        self._periods[t.value] = Tq // t_int
+        if stream_id:
+            self._carry[stream_id] = (carried + T) % t_int
         return t.value
 
     def output(self, ticket: int):
-        return self._keep[ticket][1]
+        """The ticket's output tensor; for a stream block that completes no
+        period, an empty view of it."""
+        out = self._keep[ticket][1]
+        if self._periods.get(ticket) == 0 and out.dim() == 4:
+            return out[:, :, :0]
+        return out
 
     def poll(self, ticket: int) -> JobStatus:
         st = JobStatus()
@@ -388,12 +407,14 @@ class Server:
     def release(self, ticket: int):
         _check(lib().lbf_server_release(self._h, ticket))
         self._keep.pop(ticket, None)
+        self._periods.pop(ticket, None)
 
     def close(self):
         if self._h:
             _check(lib().lbf_server_destroy(self._h))
             self._h = None
             self._keep.clear()
+            self._periods.clear()
 
     def __enter__(self):
         return self

@@ -159,3 +159,73 @@ def test_queue_status_codes():
         with pytest.raises(lbf.LbfError) as ei:
             srv.poll(tickets[0])
         assert ei.value.code == lbf.E_NOTFOUND
+
+
+# blocks of one stream whose integration periods span block boundaries: 256
+# samples cut at 100, 110, 184 (the 10-sample block completes no period)
+STREAM_CUTS = [0, 100, 110, 184, 256]
+
+
+@pytest.mark.parametrize("ctype", [lbf.F16, lbf.F32], ids=["f16", "f32"])
+def test_stream_carry_equals_the_concatenated_block(ctype):
+    torch = _torch()
+    t_int, prod = 16, lbf.STOKES_IQUV
+    streams = [synth.make_block(24, 17, 2, 16, 256, "ci8", 16.0, tag=(1105, 661, 90)),
+               synth.make_block(40, 9, 1, 8, 256, "ci16", 40.0, tag=(1105, 661, 91))]
+    xs = [to_dev(b.x) for b in streams]
+    plain = synth.make_block(24, 17, 2, 16, 64, "ci8", 16.0, tag=(1105, 661, 92))
+    with lbf.Server(_arena(64 << 20), max_inflight=8, n_streams=2, max_batch=4) as srv:
+        tickets = {0: [], 1: []}
+        # the two streams interleaved, with an independent block between them,
+        # so that consecutive blocks of a stream run on different HIP streams
+        for a, b in zip(STREAM_CUTS[:-1], STREAM_CUTS[1:]):
+            for i, (blk, x) in enumerate(zip(streams, xs)):
+                flush("server stream %d samples [%d, %d) %s" % (i, a, b, CT_NAMES[ctype]))
+                tickets[i].append(srv.submit(300 + i, blk.station_xyz, blk.beam_dir, blk.freq_hz,
+                                             x[:, :, a:b].contiguous(), ctype, prod, t_int, 1,
+                                             ref_dir=blk.ref_dir, stream_id=7 + i))
+            t_plain = _submit(srv, plain, prod, 16, 1, 310, ctype, to_dev(plain.x))
+            assert srv.wait(t_plain).state == lbf.JOB_DONE
+        for i, blk in enumerate(streams):
+            outs = []
+            for t, a, b in zip(tickets[i], STREAM_CUTS[:-1], STREAM_CUTS[1:]):
+                st = srv.wait(t)
+                assert st.state == lbf.JOB_DONE, (st.state, st.error)
+                assert st.periods == srv.output(t).shape[2]
+                outs.append(srv.output(t).clone())
+            assert [o.shape[2] for o in outs] == [6, 0, 5, 5]
+            got = torch.cat(outs, dim=2)
+            torch.cuda.synchronize()
+            ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, t_int, 1, 8)
+            g = got.cpu().numpy()
+            assert g.shape == ref.shape
+            for k in range(ref.shape[1]):
+                assert relerr(g[:, k], ref[:, k]) <= TOL[ctype], (i, k)
+
+
+def test_stream_block_rules():
+    blk = synth.make_block(24, 17, 2, 16, 40, "ci8", 16.0, tag=(1105, 661, 93))
+    x = to_dev(blk.x)
+    with lbf.Server(_arena(16 << 20), max_inflight=2, n_streams=1) as srv:
+        for bad in (dict(product=lbf.VOLTAGES, t_int=1), dict(x=blk.x)):
+            args = dict(x=x, product=lbf.STOKES_I, t_int=16)
+            args.update(bad)
+            with pytest.raises(lbf.LbfError) as ei:
+                srv.submit(1, blk.station_xyz, blk.beam_dir, blk.freq_hz, args["x"], lbf.F16, args["product"],
+                           args["t_int"], 1, ref_dir=blk.ref_dir, stream_id=5)
+            assert ei.value.code == lbf.E_INVAL
+        # 40 samples at t_int 16: two periods, 8 carried
+        t = srv.submit(1, blk.station_xyz, blk.beam_dir, blk.freq_hz, x, lbf.F16, lbf.STOKES_I, 16, 1,
+                       ref_dir=blk.ref_dir, stream_id=5)
+        st = srv.wait(t)
+        assert st.state == lbf.JOB_DONE and st.periods == 2
+        # a live stream keeps its t_int
+        with pytest.raises(lbf.LbfError) as ei:
+            srv.submit(1, blk.station_xyz, blk.beam_dir, blk.freq_hz, x, lbf.F16, lbf.STOKES_I, 8, 1,
+                       ref_dir=blk.ref_dir, stream_id=5)
+        assert ei.value.code == lbf.E_INVAL
+        # the same t_int continues it: 8 + 40 = 48 samples, three periods
+        t = srv.submit(1, blk.station_xyz, blk.beam_dir, blk.freq_hz, x, lbf.F16, lbf.STOKES_I, 16, 1,
+                       ref_dir=blk.ref_dir, stream_id=5)
+        st = srv.wait(t)
+        assert st.state == lbf.JOB_DONE and st.periods == 3
