@@ -77,6 +77,8 @@ lbf::BlockDesc to_desc(const lbf_block* b) {
     d.t_int = b->product == LBF_VOLTAGES ? 1 : b->t_int;
     d.f_int = b->product == LBF_VOLTAGES ? 1 : b->f_int;
     d.order = 0;
+    d.b0 = 0;
+    d.b1 = b->B;
     return d;
 }
 

@@ -17,6 +17,7 @@ struct BatchArgs {
     int nbg[kMaxBatch];
     int n;
 };
+static_assert(sizeof(BatchArgs) <= 4096, "kernel argument block");
 
 // Items of t_int = 16 Stokes blocks (the common integration) run the fast
 // workers; everything else in a batch runs the generic ones.
@@ -24,11 +25,14 @@ __host__ __device__ inline bool batch_fast(const BlockDesc& d) { return fast_pat
 
 template <int XT, int CT, int PR>
 LBF_INLINE void batch_item_fast(const BlockDesc& d, int item, int nbg, uint32_t* at) {
+    const int nk = fast_h_ksteps(d.S);
     if (fast_h_streams(d) == 1) {
-        if (d.S <= 32) item_h_fast<XT, CT, PR, 16, 4, 1>(d, item, nbg, at);
+        if (nk == 4) item_h_fast<XT, CT, PR, 16, 4, 1>(d, item, nbg, at);
+        else if (nk == 6) item_h_fast<XT, CT, PR, 16, 6, 1>(d, item, nbg, at);
         else item_h_fast<XT, CT, PR, 16, 8, 1>(d, item, nbg, at);
     } else {
-        if (d.S <= 32) item_h_fast<XT, CT, PR, 16, 4, 2>(d, item, nbg, at);
+        if (nk == 4) item_h_fast<XT, CT, PR, 16, 4, 2>(d, item, nbg, at);
+        else if (nk == 6) item_h_fast<XT, CT, PR, 16, 6, 2>(d, item, nbg, at);
         else item_h_fast<XT, CT, PR, 16, 8, 2>(d, item, nbg, at);
     }
 }
@@ -69,7 +73,7 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
     a.n = 0;
     a.item_start[0] = 0;
     size_t stage_bytes = 0, stage_off[kMaxBatch];
-    int src[kMaxBatch];
+    int src[kMaxBatch], nsrc = 0, entry_src[kMaxBatch];
     for (int j = 0; j < n; ++j) {
         if (!batch_fast(blks[j])) {
             const hipError_t e = launch_beamform(blks[j], st);
@@ -77,12 +81,20 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
             continue;
         }
         const int K = blks[j].product == PR_IQUV ? 4 : 1;
-        stage_off[a.n] = stage_bytes;
+        stage_off[nsrc] = stage_bytes;
         stage_bytes += ((size_t)blks[j].C * K * (blks[j].T / blks[j].t_int) * blks[j].B * sizeof(float) + 255) &
                        ~(size_t)255;
-        src[a.n] = j;
-        a.blk[a.n] = blks[j];
-        a.n++;
+        src[nsrc] = j;
+        // a beam tail of at most 128 beams becomes an entry of its own while
+        // the argument block has room (it holds kMaxBatch entries)
+        BlockDesc part[2];
+        int np = split_fast_h(blks[j], part);
+        if (a.n + np + (n - 1 - j) > kMaxBatch) np = 1, part[0] = blks[j];
+        for (int p = 0; p < np; ++p) {
+            entry_src[a.n] = nsrc;
+            a.blk[a.n++] = part[p];
+        }
+        nsrc++;
     }
     if (a.n == 0) return hipSuccess;
     // Stokes go to channel-major staging first (as in lbf_beamform), then to
@@ -91,7 +103,7 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
     hipError_t e = staging_alloc((void**)&stage, stage_bytes, st);
     if (e != hipSuccess) return e;
     for (int j = 0; j < a.n; ++j) {
-        a.blk[j].out = stage + stage_off[j];
+        a.blk[j].out = stage + stage_off[entry_src[j]];
         a.blk[j].order = 1;
         int nbg;
         const int items = block_items_fast_h(a.blk[j], &nbg);
@@ -119,7 +131,7 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
             hipLaunchKernelGGL(bf_batch_kernel<CT_BF16>, dim3(grid), dim3(kThreadsH), 0, st, a, d_counter);
         e = hipGetLastError();
     }
-    for (int j = 0; j < a.n && e == hipSuccess; ++j) {
+    for (int j = 0; j < nsrc && e == hipSuccess; ++j) {
         const BlockDesc& b = blks[src[j]];
         const int K = b.product == PR_IQUV ? 4 : 1;
         e = launch_stage_to_beam_major((const float*)(stage + stage_off[j]), b.C, K * (b.T / b.t_int), b.B,

@@ -647,7 +647,24 @@ LBF_INLINE WaveTiles wave_tiles(int wave, int T, int t_int) {
 
 // Sample streams of the fast FP16/BF16 worker: one for more than 128 beams
 // (work items of 256 beams), else two (items of 128 beams).
-__host__ __device__ inline int fast_h_streams(const BlockDesc& d) { return d.B > 128 ? 1 : 2; }
+__host__ __device__ inline int fast_h_streams(const BlockDesc& d) { return d.b1 - d.b0 > 128 ? 1 : 2; }
+
+// K-steps of 8 stations of the fast FP16/BF16 worker: 4, 6 or 8
+__host__ __device__ inline int fast_h_ksteps(int S) { return S <= 32 ? 4 : S <= 48 ? 6 : 8; }
+
+// A block whose beams beyond the last whole 256-beam group number at most 128
+// is taken in two parts: the 256-beam groups, and the rest as 128-beam items
+// (half the padding of a last 256-beam group).  Returns the number of parts
+// (1 or 2) written to part[].
+inline int split_fast_h(const BlockDesc& d, BlockDesc* part) {
+    const int nb = d.b1 - d.b0, tail = nb % 256;
+    part[0] = d;
+    if (nb <= 256 || tail == 0 || tail > 128) return 1;
+    part[0].b1 = d.b0 + (nb - tail);
+    part[1] = d;
+    part[1].b0 = part[0].b1;
+    return 2;
+}
 
 // Work items of the fast FP16/BF16 worker: (channel, group of 256/NS beams,
 // segment of up to kSegTiles 32-sample tiles) -- long blocks are cut in time
@@ -655,7 +672,7 @@ __host__ __device__ inline int fast_h_streams(const BlockDesc& d) { return d.B >
 constexpr int kSegTiles = 24;
 inline int block_items_fast_h(const BlockDesc& d, int* nbg) {
     const int per = 8 / fast_h_streams(d) * kTile;
-    *nbg = (d.B + per - 1) / per;
+    *nbg = (d.b1 - d.b0 + per - 1) / per;
     const int ntiles = (d.T + kTile - 1) / kTile;
     return d.C * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
 }

@@ -46,16 +46,20 @@ inline hipError_t launch_f32_xt(const BlockDesc& d, int nbg, int n, hipStream_t 
     return launch_f32_pr<XT, PR_IQUV>(d, nbg, n, st);
 }
 
+template <int XT, int CT, int PR, int TI, int NS>
+inline void launch_h_ns(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    const dim3 g(n), b(kThreadsH);
+    switch (fast_h_ksteps(d.S)) {
+        case 4: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4, NS>), g, b, 0, st, d, nbg, n); break;
+        case 6: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 6, NS>), g, b, 0, st, d, nbg, n); break;
+        default: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8, NS>), g, b, 0, st, d, nbg, n); break;
+    }
+}
+
 template <int XT, int CT, int PR, int TI>
 inline hipError_t launch_h_k(const BlockDesc& d, int nbg, int n, hipStream_t st) {
-    const dim3 g(n), b(kThreadsH);
-    if (fast_h_streams(d) == 1) {
-        if (d.S <= 32) hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4, 1>), g, b, 0, st, d, nbg, n);
-        else hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8, 1>), g, b, 0, st, d, nbg, n);
-    } else {
-        if (d.S <= 32) hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4, 2>), g, b, 0, st, d, nbg, n);
-        else hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8, 2>), g, b, 0, st, d, nbg, n);
-    }
+    if (fast_h_streams(d) == 1) launch_h_ns<XT, CT, PR, TI, 1>(d, nbg, n, st);
+    else launch_h_ns<XT, CT, PR, TI, 2>(d, nbg, n, st);
     return hipGetLastError();
 }
 
@@ -80,10 +84,16 @@ inline hipError_t launch_h_xt(const BlockDesc& d, int nbg, int n, hipStream_t st
 
 template <int CT>
 inline hipError_t launch_fast_h(const BlockDesc& d, hipStream_t st) {
-    int nbg;
-    const int n = block_items_fast_h(d, &nbg);
-    if (d.xtype == XT_CI8) return launch_h_xt<XT_CI8, CT>(d, nbg, n, st);
-    return launch_h_xt<XT_CI16, CT>(d, nbg, n, st);
+    BlockDesc part[2];
+    const int np = split_fast_h(d, part);
+    for (int p = 0; p < np; ++p) {
+        int nbg;
+        const int n = block_items_fast_h(part[p], &nbg);
+        const hipError_t e = d.xtype == XT_CI8 ? launch_h_xt<XT_CI8, CT>(part[p], nbg, n, st)
+                                               : launch_h_xt<XT_CI16, CT>(part[p], nbg, n, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace lbf

@@ -212,7 +212,8 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
     }
 }
 
-// FP16/BF16 operands (MFMA 32x32x16: 8 stations per K-step, NK K-steps).
+// FP16/BF16 operands (MFMA 32x32x16: 8 stations per K-step, NK K-steps:
+// 4, 6 or 8, the fewest that hold the block's stations).
 //
 // A work group of 8 waves (two per SIMD) takes one channel and NBT = 8/NS
 // beam tiles of 32 beams; its tiles of 32 samples are split into NS streams.
@@ -273,8 +274,8 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int r = lane & 31, h = lane >> 5;
     const int bt = wave % NBT, sigma = wave / NBT;         // beam tile, sample stream
-    const int S = d.S, B = d.B;
-    const int beam = (bg * NBT + bt) * kTile + r;
+    const int S = d.S, B = d.B, bend = d.b1;
+    const int beam = d.b0 + (bg * NBT + bt) * kTile + r;
     const int nsteps = (ntiles + NS - 1) / NS;
     const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
     constexpr int K = PR == PR_IQUV ? 4 : 1;
@@ -344,7 +345,6 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     // the last two slices.
     const int trow = tile_row_sample(r);
     const int sw = a_swz(trow);
-    constexpr int SPS = 16 / NK;                           // epilogue samples per slice
     constexpr bool PIPE = !(XT == XT_CI16 && NS == 2);     // two accumulator sets
     constexpr int NOUT = PR == PR_VOLT ? 1 : 16 / TI;
     auto step = [&](int k, floatx16 (&acc)[4], const floatx16 (&prev)[4]) {
@@ -356,7 +356,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
         ax[0] = *reinterpret_cast<const u32x4*>(ax0 + 4 * (h ^ sw));
         ay[0] = *reinterpret_cast<const u32x4*>(ax0 + kARow + 4 * (h ^ sw));
         const int tprev = tile_lo + sigma + NS * (k - 1);
-        const bool okprev = k >= 1 && tprev < tile_lo + ntiles && beam < B;
+        const bool okprev = k >= 1 && tprev < tile_lo + ntiles && beam < bend;
         float sm[NOUT][4];
 #pragma unroll
         for (int o = 0; o < NOUT; ++o)
@@ -375,10 +375,9 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
             acc[1] = MfmaH<CT>::mfma(a, bi, kk == 0 ? zero16() : acc[1]);
             acc[2] = MfmaH<CT>::mfma(b, br, kk == 0 ? zero16() : acc[2]);
             acc[3] = MfmaH<CT>::mfma(b, bi, kk == 0 ? zero16() : acc[3]);
-            // epilogue slice: samples [kk SPS, (kk+1) SPS) of the previous tile
+            // epilogue slice: samples [16 kk / NK, 16 (kk + 1) / NK) of the previous tile
 #pragma unroll
-            for (int js = 0; js < SPS; ++js) {
-                const int smp = kk * SPS + js;
+            for (int smp = 16 * kk / NK; smp < 16 * (kk + 1) / NK; ++smp) {
                 if (PR == PR_VOLT) {
                     const int t = tprev * kTile + 16 * h + smp;
                     const uint32_t off = store_off(okprev && t < T, ((uint32_t)beam * T + t) * 16u);
@@ -426,7 +425,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     // the last tile's epilogue: one more step without MFMAs
     auto final_epilogue = [&](const floatx16 (&prev)[4], int klast) {
         const int tile = tile_lo + sigma + NS * klast;
-        const bool ok = klast >= 0 && tile < tile_lo + ntiles && beam < B;
+        const bool ok = klast >= 0 && tile < tile_lo + ntiles && beam < bend;
         if (PR == PR_VOLT) volt_store_cm(prev, ors, T, beam, tile * kTile, h, ok);
         else stokes_store_cm<PR, TI>(prev, ors, B, T2, beam, tile * kTile, h, ok);
     };
