@@ -17,6 +17,39 @@ namespace lbf {
 constexpr double kC0 = 299792458.0;
 constexpr int kWChan = 32;
 
+// cos(2 pi r) and sin(2 pi r) for |r| <= 1/2, in FP64.  Quarter-turn
+// reduction r = q/4 + u (q = rint(4r), |u| <= 1/8, u exact), then the Taylor
+// series of sin and cos at theta = 2 pi u (|theta| <= pi/4, so the first
+// omitted terms, theta^17/17! and theta^18/18!, are below 5e-17), then the
+// quadrant q mod 4 by symmetry.  About twenty FP64 operations instead of a
+// general-argument library call.
+__device__ inline void cis_turn(double r, double* c, double* s) {
+    const double q = rint(4.0 * r);
+    const double u = __builtin_fma(q, -0.25, r);
+    const double th = u * 6.283185307179586;
+    const double t2 = th * th;
+    double ps = -1.0 / 1307674368000.0;                   // -1/15!
+    ps = __builtin_fma(ps, t2, 1.0 / 6227020800.0);       //  1/13!
+    ps = __builtin_fma(ps, t2, -1.0 / 39916800.0);        // -1/11!
+    ps = __builtin_fma(ps, t2, 1.0 / 362880.0);           //  1/9!
+    ps = __builtin_fma(ps, t2, -1.0 / 5040.0);            // -1/7!
+    ps = __builtin_fma(ps, t2, 1.0 / 120.0);              //  1/5!
+    ps = __builtin_fma(ps, t2, -1.0 / 6.0);               // -1/3!
+    const double sn = __builtin_fma(th * t2, ps, th);
+    double pc = 1.0 / 20922789888000.0;                   //  1/16!
+    pc = __builtin_fma(pc, t2, -1.0 / 87178291200.0);     // -1/14!
+    pc = __builtin_fma(pc, t2, 1.0 / 479001600.0);        //  1/12!
+    pc = __builtin_fma(pc, t2, -1.0 / 3628800.0);         // -1/10!
+    pc = __builtin_fma(pc, t2, 1.0 / 40320.0);            //  1/8!
+    pc = __builtin_fma(pc, t2, -1.0 / 720.0);             // -1/6!
+    pc = __builtin_fma(pc, t2, 1.0 / 24.0);               //  1/4!
+    pc = __builtin_fma(pc, t2, -0.5);                     // -1/2!
+    const double cs = __builtin_fma(t2, pc, 1.0);
+    const int quad = (int)q & 3;
+    *c = quad == 0 ? cs : quad == 1 ? -sn : quad == 2 ? -cs : sn;
+    *s = quad == 0 ? sn : quad == 1 ? cs : quad == 2 ? -sn : -cs;
+}
+
 template <int WT>
 __global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__ pos, int S,
                                                       const double* __restrict__ dir, int B, double rx, double ry,
@@ -35,7 +68,7 @@ __global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__
         const double m = freq[c] * t;
         const double r = m - rint(m);          // fractional turn in [-0.5, 0.5]
         double sn, cs;
-        sincospi(2.0 * r, &sn, &cs);
+        cis_turn(r, &cs, &sn);
         const double wr = cs, wi = -sn;
         const size_t i = (size_t)c * BS + bs;
         if (WT == CT_F32) {
@@ -160,23 +193,32 @@ hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int el
 }
 
 // ---------------------------------------------------------------------------
-// Beam-fastest staging s[c][m][b] -> final order out[b][m][c] (m = k*T' + t',
-// Section 4.6).  Each work group moves a 64-channel x 64-beam tile of one m
-// through LDS: reads are 256-byte runs along b, writes 256-byte runs along c,
-// 16 bytes per lane where the rows allow it (VEC: B and C2 multiples of 4).
+// Beam-fastest staging s[c][m][b] (rows of ldb >= B beams) -> final order
+// out[b][m][c] (m = k*T' + t', Section 4.6).  Each work group moves a
+// 64-channel x 64-beam tile of one m through LDS: reads are 256-byte runs
+// along b, writes 256-byte runs along c, 16 bytes per lane where the rows allow
+// it (VEC: ldb and C2 multiples of 4).  With ldb a multiple of 32 every read
+// run starts on a 128-byte line.  The order in which the grid walks the tiles
+// (`walk`) is the one measured fastest for the row alignment: 0 m, channel
+// tile, beam tile (any M); 1 channel tile, m, beam tile (128-byte-aligned
+// rows); 2 beam tile, channel tile, m (other rows).
 // ---------------------------------------------------------------------------
 template <bool VEC>
 __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* __restrict__ in, int C2, int M, int B,
-                                                                  float* __restrict__ out) {
+                                                                  int ldb, float* __restrict__ out, int walk) {
     __shared__ float tile[64][65];
-    const int b0 = blockIdx.z * 64, c0 = blockIdx.y * 64;
-    const size_t m = blockIdx.x;
+    int bt, ct;
+    size_t m;
+    if (walk == 0) { m = blockIdx.x; ct = blockIdx.y; bt = blockIdx.z; }
+    else if (walk == 1) { ct = blockIdx.x; m = blockIdx.y; bt = blockIdx.z; }
+    else { bt = blockIdx.x; ct = blockIdx.y; m = blockIdx.z; }
+    const int b0 = bt * 64, c0 = ct * 64;
     const int q = threadIdx.x & 15, rr = threadIdx.x >> 4;       // 16 lanes x 4 elements per row
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int r = p * 16 + rr, c = c0 + r, b = b0 + 4 * q;
         if (c >= C2) continue;
-        const float* src = in + ((size_t)c * M + m) * B + b;
+        const float* src = in + ((size_t)c * M + m) * ldb + b;
         if (VEC && b + 3 < B) {
             const float4 v = *reinterpret_cast<const float4*>(src);
             tile[r][4 * q + 0] = v.x;
@@ -210,13 +252,15 @@ __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* _
     }
 }
 
-hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, float* out, hipStream_t st) {
-    dim3 g((unsigned)M, (unsigned)((C2 + 63) / 64), (unsigned)((B + 63) / 64)), b(256);
+hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, int ldb, float* out, hipStream_t st) {
+    const unsigned nm = (unsigned)M, nc = (unsigned)((C2 + 63) / 64), nb = (unsigned)((B + 63) / 64);
+    const int walk = M > 65535 || nc > 65535 ? 0 : ldb % 32 == 0 ? 1 : 2;
+    const dim3 g = walk == 0 ? dim3(nm, nc, nb) : walk == 1 ? dim3(nc, nm, nb) : dim3(nb, nc, nm), b(256);
     const bool aligned = ((reinterpret_cast<uintptr_t>(stage) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
-    if (aligned && B % 4 == 0 && C2 % 4 == 0)
-        hipLaunchKernelGGL(stage_to_beam_major_kernel<true>, g, b, 0, st, stage, C2, M, B, out);
+    if (aligned && ldb % 4 == 0 && C2 % 4 == 0)
+        hipLaunchKernelGGL(stage_to_beam_major_kernel<true>, g, b, 0, st, stage, C2, M, B, ldb, out, walk);
     else
-        hipLaunchKernelGGL(stage_to_beam_major_kernel<false>, g, b, 0, st, stage, C2, M, B, out);
+        hipLaunchKernelGGL(stage_to_beam_major_kernel<false>, g, b, 0, st, stage, C2, M, B, ldb, out, walk);
     return hipGetLastError();
 }
 

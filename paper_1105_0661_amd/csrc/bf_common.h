@@ -506,7 +506,7 @@ LBF_INLINE __amdgpu_buffer_rsrc_t channel_rsrc(void* out, int c, uint32_t bytes_
 
 // Stokes of one 32x32 tile into channel-major s[k][t'][b] of its channel
 template <int PR, int TI>
-LBF_INLINE void stokes_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t rs, int B, int T2, int beam, int t0,
+LBF_INLINE void stokes_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t rs, int ldb, int T2, int beam, int t0,
                                 int h, bool ok) {
     constexpr int K = PR == PR_IQUV ? 4 : 1;
     constexpr int NOUT = 16 / TI;
@@ -520,7 +520,7 @@ LBF_INLINE void stokes_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t
         const bool st = ok && tq < T2;
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) {
-            const uint32_t off = store_off(st, (((uint32_t)kk * T2 + tq) * (uint32_t)B + beam) * 4u);
+            const uint32_t off = store_off(st, (((uint32_t)kk * T2 + tq) * (uint32_t)ldb + beam) * 4u);
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[kk]), rs, (int)off, 0, 0);
         }
     }
@@ -619,9 +619,9 @@ LBF_INLINE EpiCtx make_epi(const BlockDesc& d, int PR_, int g) {
         e.sb = (size_t)e.K * e.T2 * e.C2;
     } else {                     // [C'][K][T'][B]
         e.sb = 1;
-        e.st = (size_t)d.B;
-        e.sk = (size_t)e.T2 * d.B;
-        e.sc = (size_t)e.K * e.T2 * d.B;
+        e.st = (size_t)d.ldb;
+        e.sk = (size_t)e.T2 * d.ldb;
+        e.sc = (size_t)e.K * e.T2 * d.ldb;
     }
     return e;
 }
@@ -691,6 +691,10 @@ inline int block_items(const BlockDesc& d, int* nbg) {
     return ngroups_c * *nbg;
 }
 
+// Beams per row of the internal channel-major Stokes staging: a multiple of
+// 32 floats, so that every row starts on a 128-byte line
+__host__ __device__ constexpr int staging_ldb(int B) { return (B + 31) & ~31; }
+
 __host__ __device__ constexpr int sample_bytes(int xtype) { return xtype == XT_CI8 ? 4 : xtype == XT_CI16 ? 8 : 16; }
 
 // The fast workers take up to 64 stations of complex int8/int16 samples,
@@ -702,7 +706,7 @@ __host__ __device__ inline bool fast_path(const BlockDesc& d) {
     if (d.product != PR_VOLT && (d.t_int > 16 || d.f_int != 1)) return false;
     // one channel's output (addressed with 32-bit buffer offsets, 2^31 = "no store")
     const double out_ch = d.product == PR_VOLT ? 16.0 * d.B * (double)d.T
-                                               : 4.0 * d.product * d.B * (double)(d.T / d.t_int);
+                                               : 4.0 * d.product * staging_ldb(d.B) * (double)(d.T / d.t_int);
     if (out_ch >= 2147483648.0 - 4096.0) return false;
     return 8.0 * (double)d.C * (double)d.T * sample_bytes(d.xtype) < 2147483648.0 - 4096.0;
 }

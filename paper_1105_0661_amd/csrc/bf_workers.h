@@ -80,7 +80,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
     const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
     const int T2 = PR == PR_VOLT ? T : T / TI;
     const __amdgpu_buffer_rsrc_t ors =
-        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)K * T2 * B * 4u);
+        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)K * T2 * d.ldb * 4u);
     const int trow = tile_row_sample(r);
 
     stage_weights_f32_planes(pl, d, c, b0);
@@ -179,7 +179,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
 #pragma unroll
                 for (int kq = 0; kq < K; ++kq) {
                     const uint32_t off =
-                        store_off(okprev && beam < B && tq < T2, (((uint32_t)kq * T2 + tq) * (uint32_t)B + beam) * 4u);
+                        store_off(okprev && beam < B && tq < T2, (((uint32_t)kq * T2 + tq) * (uint32_t)d.ldb + beam) * 4u);
                     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[kq]), ors, (int)off, 0, 0);
                 }
             }
@@ -189,7 +189,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
         const int tile = tile_of(klast);
         const bool ok = klast >= 0 && beam < B;
         if (PR == PR_VOLT) volt_store_cm(prev, ors, T, beam, tile * kTile, h, ok);
-        else stokes_store_cm<PR, TI>(prev, ors, B, T2, beam, tile * kTile, h, ok);
+        else stokes_store_cm<PR, TI>(prev, ors, d.ldb, T2, beam, tile * kTile, h, ok);
     };
 
     load_quad(0, 0, 0);
@@ -281,7 +281,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     constexpr int K = PR == PR_IQUV ? 4 : 1;
     const int T2 = PR == PR_VOLT ? T : T / TI;
     const __amdgpu_buffer_rsrc_t ors =
-        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)K * T2 * B * 4u);
+        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)K * T2 * d.ldb * 4u);
 
     // this wave's weights, both variants, all K-steps
     u32x4 wr[NK], wi[NK];
@@ -415,7 +415,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
                 const int tq = tq0 + o;
 #pragma unroll
                 for (int kq = 0; kq < K; ++kq) {
-                    const uint32_t off = store_off(okprev && tq < T2, (((uint32_t)kq * T2 + tq) * (uint32_t)B + beam) * 4u);
+                    const uint32_t off = store_off(okprev && tq < T2, (((uint32_t)kq * T2 + tq) * (uint32_t)d.ldb + beam) * 4u);
                     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[kq]), ors, (int)off, 0, 0);
                 }
             }
@@ -427,7 +427,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
         const int tile = tile_lo + sigma + NS * klast;
         const bool ok = klast >= 0 && tile < tile_lo + ntiles && beam < bend;
         if (PR == PR_VOLT) volt_store_cm(prev, ors, T, beam, tile * kTile, h, ok);
-        else stokes_store_cm<PR, TI>(prev, ors, B, T2, beam, tile * kTile, h, ok);
+        else stokes_store_cm<PR, TI>(prev, ors, d.ldb, T2, beam, tile * kTile, h, ok);
     };
 
     load_chunks(0);
