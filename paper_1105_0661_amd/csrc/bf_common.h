@@ -45,6 +45,12 @@ template <> struct Raw<XT_CI8> {
         return r;
     }
     LBF_INLINE static type zero() { return 0; }
+    // the re (h = 0) or im (h = 1) part of X and of Y; sh = 8 h, kept opaque
+    // by the caller so that it stays one shift per value rather than a select
+    LBF_INLINE static void half(type v, uint32_t sh, float& x, float& y) {
+        x = (float)(int8_t)((uint32_t)v >> sh);
+        y = (float)(int8_t)((uint32_t)v >> (sh + 16u));
+    }
 };
 template <> struct Raw<XT_CI16> {
     typedef shortx4 type;
@@ -58,12 +64,23 @@ template <> struct Raw<XT_CI16> {
         return r;
     }
     LBF_INLINE static type zero() { type z = {0, 0, 0, 0}; return z; }
+    // as Raw<XT_CI8>::half, sh = 16 h
+    LBF_INLINE static void half(type v, uint32_t sh, float& x, float& y) {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 w = __builtin_bit_cast(u32x2, v);
+        x = (float)(int16_t)(w[0] >> sh);
+        y = (float)(int16_t)(w[1] >> sh);
+    }
 };
 template <> struct Raw<XT_CF32> {
     typedef floatx4 type;
     LBF_INLINE static type load(const void* p, size_t i) { return reinterpret_cast<const floatx4*>(p)[i]; }
     LBF_INLINE static floatx4 cvt(type v) { return v; }
     LBF_INLINE static type zero() { type z = {0.f, 0.f, 0.f, 0.f}; return z; }
+    LBF_INLINE static void half(type v, uint32_t sh, float& x, float& y) {
+        x = sh ? v[1] : v[0];
+        y = sh ? v[3] : v[2];
+    }
 };
 
 // ---------------------------------------------------------------------------

@@ -90,6 +90,9 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
     int wro = (h ? kPlaneWords : 0) + (bt * kTile + r) * kWRow;
     int wio = (h ? 0 : 2 * kPlaneWords) + (bt * kTile + r) * kWRow;
     __asm__ volatile("" : "+v"(wro), "+v"(wio));
+    // bit offset of this lane half's component in a raw sample word
+    uint32_t hsh = (uint32_t)h * (XT == XT_CI8 ? 8u : 16u);
+    __asm__ volatile("" : "+v"(hsh));
 
     auto tile_of = [&](int k) { return tile_lo + ts + 2 * k; };
     // Two-deep ring of 8-station groups: group n of the wave's sequence
@@ -140,11 +143,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
                     const int s4 = 8 * gi + 4 * i4;
                     float ax[4], ay[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const floatx4 v = R::cvt(ring[gi & 1][4 * i4 + i]);
-                        ax[i] = h ? v[1] : v[0];
-                        ay[i] = h ? v[3] : v[2];
-                    }
+                    for (int i = 0; i < 4; ++i) R::half(ring[gi & 1][4 * i4 + i], hsh, ax[i], ay[i]);
                     load_quad(gi & 1, i4, k * ngrp + gi + 2);
                     __builtin_amdgcn_sched_barrier(0);
                     const floatx4 br = *reinterpret_cast<const floatx4*>(pl + wro + s4);
