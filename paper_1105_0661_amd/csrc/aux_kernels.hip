@@ -21,33 +21,56 @@ constexpr int kWChan = 32;
 // reduction r = q/4 + u (q = rint(4r), |u| <= 1/8, u exact), then the Taylor
 // series of sin and cos at theta = 2 pi u (|theta| <= pi/4, so the first
 // omitted terms, theta^17/17! and theta^18/18!, are below 5e-17), then the
-// quadrant q mod 4 by symmetry.  About twenty FP64 operations instead of a
-// general-argument library call.
-__device__ inline void cis_turn(double r, double* c, double* s) {
+// quadrant q mod 4 by symmetry: swap for odd q, and sign flips.  About twenty
+// FP64 operations instead of a general-argument library call.
+struct CisCoef {
+    double s[7];   // -1/15!, 1/13!, ..., -1/3!  (Horner order)
+    double c[8];   //  1/16!, -1/14!, ..., -1/2!
+};
+
+__device__ inline CisCoef cis_coef() {
+    CisCoef k;
+    k.s[0] = -1.0 / 1307674368000.0;
+    k.s[1] = 1.0 / 6227020800.0;
+    k.s[2] = -1.0 / 39916800.0;
+    k.s[3] = 1.0 / 362880.0;
+    k.s[4] = -1.0 / 5040.0;
+    k.s[5] = 1.0 / 120.0;
+    k.s[6] = -1.0 / 6.0;
+    k.c[0] = 1.0 / 20922789888000.0;
+    k.c[1] = -1.0 / 87178291200.0;
+    k.c[2] = 1.0 / 479001600.0;
+    k.c[3] = -1.0 / 3628800.0;
+    k.c[4] = 1.0 / 40320.0;
+    k.c[5] = -1.0 / 720.0;
+    k.c[6] = 1.0 / 24.0;
+    k.c[7] = -0.5;
+    return k;
+}
+
+// (cos 2 pi r, -sin 2 pi r): the weight of a fractional turn r
+__device__ inline void weight_of_turn(double r, const CisCoef& k, double* wr, double* wi) {
     const double q = rint(4.0 * r);
     const double u = __builtin_fma(q, -0.25, r);
     const double th = u * 6.283185307179586;
     const double t2 = th * th;
-    double ps = -1.0 / 1307674368000.0;                   // -1/15!
-    ps = __builtin_fma(ps, t2, 1.0 / 6227020800.0);       //  1/13!
-    ps = __builtin_fma(ps, t2, -1.0 / 39916800.0);        // -1/11!
-    ps = __builtin_fma(ps, t2, 1.0 / 362880.0);           //  1/9!
-    ps = __builtin_fma(ps, t2, -1.0 / 5040.0);            // -1/7!
-    ps = __builtin_fma(ps, t2, 1.0 / 120.0);              //  1/5!
-    ps = __builtin_fma(ps, t2, -1.0 / 6.0);               // -1/3!
+    double ps = k.s[0];
+#pragma unroll
+    for (int i = 1; i < 7; ++i) ps = __builtin_fma(ps, t2, k.s[i]);
     const double sn = __builtin_fma(th * t2, ps, th);
-    double pc = 1.0 / 20922789888000.0;                   //  1/16!
-    pc = __builtin_fma(pc, t2, -1.0 / 87178291200.0);     // -1/14!
-    pc = __builtin_fma(pc, t2, 1.0 / 479001600.0);        //  1/12!
-    pc = __builtin_fma(pc, t2, -1.0 / 3628800.0);         // -1/10!
-    pc = __builtin_fma(pc, t2, 1.0 / 40320.0);            //  1/8!
-    pc = __builtin_fma(pc, t2, -1.0 / 720.0);             // -1/6!
-    pc = __builtin_fma(pc, t2, 1.0 / 24.0);               //  1/4!
-    pc = __builtin_fma(pc, t2, -0.5);                     // -1/2!
+    double pc = k.c[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) pc = __builtin_fma(pc, t2, k.c[i]);
     const double cs = __builtin_fma(t2, pc, 1.0);
-    const int quad = (int)q & 3;
-    *c = quad == 0 ? cs : quad == 1 ? -sn : quad == 2 ? -cs : sn;
-    *s = quad == 0 ? sn : quad == 1 ? cs : quad == 2 ? -sn : -cs;
+    // quadrant q (mod 4): (cos, sin) = (c, s), (-s, c), (-c, -s), (s, -c)
+    const int quad = (int)q;
+    const bool odd = (quad & 1) != 0;
+    const uint64_t x = __builtin_bit_cast(uint64_t, odd ? sn : cs);
+    const uint64_t y = __builtin_bit_cast(uint64_t, odd ? cs : sn);
+    const uint64_t negx = (uint64_t)((quad + 1) & 2) << 62;
+    const uint64_t negy = ((uint64_t)(quad & 2) << 62) ^ 0x8000000000000000ull;   // and -sin
+    *wr = __builtin_bit_cast(double, x ^ negx);
+    *wi = __builtin_bit_cast(double, y ^ negy);
 }
 
 template <int WT>
@@ -64,12 +87,17 @@ __global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__
     if (tau != nullptr && blockIdx.y == 0) tau[bs] = t;
     const int c0 = blockIdx.y * kWChan, c1 = min(C, c0 + kWChan);
     const size_t BS = (size_t)B * S;
+    // the series coefficients stay in registers across the channel loop
+    CisCoef k = cis_coef();
+#pragma unroll
+    for (int i = 0; i < 7; ++i) __asm__ volatile("" : "+v"(k.s[i]));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) __asm__ volatile("" : "+v"(k.c[i]));
     for (int c = c0; c < c1; ++c) {
         const double m = freq[c] * t;
         const double r = m - rint(m);          // fractional turn in [-0.5, 0.5]
-        double sn, cs;
-        cis_turn(r, &cs, &sn);
-        const double wr = cs, wi = -sn;
+        double wr, wi;
+        weight_of_turn(r, k, &wr, &wi);
         const size_t i = (size_t)c * BS + bs;
         if (WT == CT_F32) {
             float2 v;

@@ -78,10 +78,17 @@ template <> struct Sample<XT_CF32> {
 // Going through float with round-to-odd keeps one rounding: float carries
 // 24 significand bits, at least 2 more than f16 (11) or bf16 (8).
 // ---------------------------------------------------------------------------
+// Round-to-odd from the round-to-nearest result f: when d is not exact in
+// float it lies strictly between two neighbouring floats, one of them odd
+// (in the bit pattern) -- the round-to-odd result.  f is one of the two; if f
+// is even, the odd one is the neighbour on d's side, one bit pattern step
+// away.  For finite d of at most float range (weights have |d| <= 1).
 __device__ inline float f64_to_f32_round_odd(double d) {
-    float f = __double2float_rz(d);
-    if ((double)f != d) f = __uint_as_float(__float_as_uint(f) | 1u);
-    return f;
+    const float f = (float)d;
+    const uint32_t u = __float_as_uint(f);
+    const bool step = (double)f != d && (u & 1u) == 0u;
+    const uint32_t toward_zero = __builtin_fabs((double)f) > __builtin_fabs(d) ? 0xffffffffu : 1u;
+    return __uint_as_float(step ? u + toward_zero : u);
 }
 
 __device__ inline uint16_t f32_to_bf16_bits(float f) {
