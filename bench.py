@@ -98,6 +98,47 @@ def time_path(lbf, torch, x, geo, ctype, product, t_int, f_int, steps, warmup):
                 reorder_ms=span(2, 3), out=out, w=w)
 
 
+def unfused(lbf, torch, x, geo, nch, steps, warmup):
+    """The unfused chain on the first `nch` channels of a block: FP32 voltages
+    (lbf_beamform VOLTAGES), Stokes IQUV integrated x16 (lbf_stokes) and the
+    final order (lbf_transpose), each timed with HIP events on the current
+    stream, against the fused product of the same channels."""
+    pos, dirs, freq, ref = geo
+    xs = x[:, :nch].contiguous()
+    S, C, T = xs.shape[:3]
+    B = dirs.shape[0]
+    w = lbf.compute_weights(pos, dirs, freq[:nch].contiguous(), lbf.F32, ref_dir=ref)
+    n = warmup + steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n)]
+    y = s = o = None
+    for i in range(n):
+        ev[i][0].record()
+        y = lbf.beamform(xs, w, lbf.VOLTAGES, out=y)
+        ev[i][1].record()
+        s = lbf.stokes(y, lbf.STOKES_IQUV, 16, 1, out=s)
+        ev[i][2].record()
+        o = lbf.transpose(s, out=o)
+        ev[i][3].record()
+    fused = lbf.beamform(xs, w, lbf.STOKES_IQUV, 16, 1)
+    torch.cuda.synchronize()
+
+    def span(a, b):
+        return float(np.mean([ev[i][a].elapsed_time(ev[i][b]) for i in range(warmup, n)]))
+
+    v_ms, s_ms, t_ms = span(0, 1), span(1, 2), span(2, 3)
+    y_bytes = C * B * T * 16
+    s_bytes = C * B * (T // 16) * 4 * 4
+    v_bytes = S * C * T * 8 + C * B * S * 8 + y_bytes
+    err = relerr(o.cpu().numpy(), fused.cpu().numpy())
+    del xs, y, s, o, fused
+    return {"workload": "first %d channels of the one-second block, FP32 voltages -> Stokes IQUV x16 -> final order"
+                        % nch,
+            "voltages_kernel_ms": v_ms, "voltages_hbm_GBps": v_bytes / (v_ms / 1e3) / 1e9,
+            "stokes_kernel_ms": s_ms, "stokes_hbm_GBps": (y_bytes + s_bytes) / (s_ms / 1e3) / 1e9,
+            "transpose_kernel_ms": t_ms, "transpose_hbm_GBps": 2 * s_bytes / (t_ms / 1e3) / 1e9,
+            "rel_err_vs_fused": err}
+
+
 def t_roof_s(fp):
     """Roofline time of one FP16-MFMA block: max(MFMA, HBM) at the datasheet peaks."""
     return max(fp.flops / (PEAK["f16_TFLOPs"] * 1e12),
@@ -374,8 +415,10 @@ def main():
 
     # ---------------- the 488-beam precision block (MFMA-bound) ----------------
     extra = None
-    batch_res = serve_res = None
+    batch_res = serve_res = unfused_res = None
     if not a.no_extra and not only:
+        unfused_res = unfused(lbf, torch, x, geo, 1024, max(3, a.steps // 4), 1)
+        log("unfused chain: %s" % unfused_res)
         b2 = synth.config2(threads=16)
         x2 = torch.from_numpy(b2.x).to(dev)
         geo2 = (torch.from_numpy(b2.station_xyz).to(dev), torch.from_numpy(b2.beam_dir).to(dev),
@@ -465,6 +508,8 @@ def main():
         line["fp16_mfma_vs_fp32_speedup"] = paths["f16"]["beam_samples_per_s"] / paths["f32"]["beam_samples_per_s"]
     if extra:
         line["precision_block"] = extra
+    if unfused_res:
+        line["unfused_chain"] = unfused_res
     if batch_res:
         line["batched"] = batch_res
     if serve_res:

@@ -163,13 +163,80 @@ __global__ __launch_bounds__(256) void stokes_kernel(const floatx4* __restrict__
     }
 }
 
+// Power-of-two t_int: G = min(t_int, 64) consecutive lanes share an output
+// (c', b, t').  Lane g reads samples t'*t_int + g + G*j (j < t_int/G) of the
+// f_int channels, so a wave's loads are 64 consecutive 16-byte samples of one
+// (c, b) row; the G partial sums meet in a butterfly of lane exchanges and
+// lane g = 0 stores them.  Sum order: channel, then the lane's samples, then
+// the butterfly.
+template <int K>
+__global__ __launch_bounds__(256) void stokes_wave_kernel(const floatx4* __restrict__ y, int B, int C, int T,
+                                                          int t_int, int f_int, float* __restrict__ s) {
+    const int T2 = T / t_int, C2 = C / f_int;
+    const int G = t_int < kWave ? t_int : kWave;
+    const size_t slots = (size_t)C2 * B * T2 * G;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i - threadIdx.x % kWave < slots;
+         i += (size_t)gridDim.x * blockDim.x) {
+        // whole waves stay in the loop together (the exchanges need every
+        // lane); lanes past the end add zeros and store nothing
+        const bool live = i < slots;
+        const size_t o = live ? i / G : 0;
+        const int g = (int)(i % G);
+        const int t2 = (int)(o % T2);
+        const size_t cb = o / T2;
+        const int b = (int)(cb % B);
+        const int c2 = (int)(cb / B);
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        if (live) {
+            for (int dc = 0; dc < f_int; ++dc) {
+                const floatx4* row = y + ((size_t)(c2 * f_int + dc) * B + b) * T + (size_t)t2 * t_int + g;
+                for (int j = 0; j < t_int / G; ++j) {
+                    const floatx4 v = row[(size_t)j * G];
+                    const float xx = v[0] * v[0] + v[1] * v[1];
+                    const float yy = v[2] * v[2] + v[3] * v[3];
+                    acc[0] += xx + yy;
+                    if (K == 4) {
+                        acc[1] += xx - yy;
+                        acc[2] += 2.0f * (v[0] * v[2] + v[1] * v[3]);
+                        acc[3] += 2.0f * (v[1] * v[2] - v[0] * v[3]);
+                    }
+                }
+            }
+        }
+        for (int m = G / 2; m >= 1; m /= 2)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += __shfl_xor(acc[k], m, kWave);
+        if (live && g == 0) {
+            if (K == 4) {
+                floatx4 v;
+                v[0] = acc[0]; v[1] = acc[1]; v[2] = acc[2]; v[3] = acc[3];
+                reinterpret_cast<floatx4*>(s)[o] = v;
+            } else {
+                s[o] = acc[0];
+            }
+        }
+    }
+}
+
 hipError_t launch_stokes(const float* y, int B, int C, int T, int product, int t_int, int f_int, float* s,
                          hipStream_t st) {
+    const floatx4* yy = reinterpret_cast<const floatx4*>(y);
+    if ((t_int & (t_int - 1)) == 0) {
+        const size_t slots = (size_t)(C / f_int) * B * (T / t_int) * (t_int < kWave ? t_int : kWave);
+        size_t blocks = (slots + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        if (product == PR_IQUV)
+            hipLaunchKernelGGL(stokes_wave_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, yy, B, C, T, t_int,
+                               f_int, s);
+        else
+            hipLaunchKernelGGL(stokes_wave_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, yy, B, C, T, t_int,
+                               f_int, s);
+        return hipGetLastError();
+    }
     const size_t n = (size_t)(C / f_int) * B * (T / t_int);
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks == 0) blocks = 1;
-    const floatx4* yy = reinterpret_cast<const floatx4*>(y);
     if (product == PR_IQUV)
         hipLaunchKernelGGL(stokes_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, yy, B, C, T, t_int, f_int, s);
     else
