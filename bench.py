@@ -139,6 +139,30 @@ def unfused(lbf, torch, x, geo, nch, steps, warmup):
             "rel_err_vs_fused": err}
 
 
+def measured_peaks(lbf, torch, dev):
+    """What this device sustains: register-only MFMA loops in the contraction's
+    instruction forms (FP16 32x32x16, FP32 32x32x2) and a 4 GiB device copy,
+    each timed with HIP events (lbf_probe)."""
+    sink = torch.empty(512, dtype=torch.float32, device=dev)
+    src = torch.empty(1 << 30, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    out = {}
+    for name, kind, iters, scale in (("f16_TFLOPs", lbf.PROBE_MFMA_F16, 16000, 1e12),
+                                     ("f32_TFLOPs", lbf.PROBE_MFMA_F32, 8000, 1e12),
+                                     ("hbm_GBps", lbf.PROBE_COPY, 1, 1e9)):
+        s_, d_ = (src, dst) if kind == lbf.PROBE_COPY else (None, sink)
+        lbf.probe(kind, max(1, iters // 4), s_, d_)                # warm-up (clocks)
+        reps = 10 if kind == lbf.PROBE_COPY else 2
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        work = sum(lbf.probe(kind, iters, s_, d_) for _ in range(reps))
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = work / (e0.elapsed_time(e1) / 1e3) / scale
+    del src, dst
+    return out
+
+
 def t_roof_s(fp):
     """Roofline time of one FP16-MFMA block: max(MFMA, HBM) at the datasheet peaks."""
     return max(fp.flops / (PEAK["f16_TFLOPs"] * 1e12),
@@ -382,6 +406,9 @@ def main():
             name, np.median(r["step_ms"]), np.median(r["weights_ms"]), np.median(r["beamform_ms"]),
             np.median(r["reorder_ms"])))
         res[name] = r
+    mp = None if only else measured_peaks(lbf, torch, dev)
+    if mp:
+        log("measured peaks: %s" % mp)
 
     # ---------------- oracle on sampled subbands (CPU baseline + errors) ----------------
     cpu = None
@@ -435,6 +462,8 @@ def main():
                            "weights_kernel_ms": float(np.mean(r["weights_ms"])),
                            "mfma_TFLOPs": fp2.flops / (kms / 1e3) / 1e12,
                            "mfma_frac": fp2.flops / (kms / 1e3) / 1e12 / PEAK["f16_TFLOPs"]}
+            if mp:
+                extra[name]["mfma_frac_of_measured_peak"] = extra[name]["mfma_TFLOPs"] / mp["f16_TFLOPs"]
             log("precision %s: %s" % (name, extra[name]))
         del b2.x
 
@@ -484,6 +513,7 @@ def main():
                      "kernel": "bf_f32_fast_kernel<ci16, IQUV, t_int 16>", "kernel_ms": kms,
                      "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_sources": kernel_source_hash()},
+        "measured_peaks": mp,
         "cpu_baseline": cpu,
     }
     paths = {}
@@ -501,9 +531,13 @@ def main():
             byts = fpn.input_bytes + fpn.weight_bytes + fpn.output_bytes
             ent["hbm_GBps"] = byts / (k / 1e3) / 1e9
             ent["hbm_frac"] = ent["hbm_GBps"] / PEAK["hbm_GBps"]
+            if mp:
+                ent["hbm_frac_of_measured_copy"] = ent["hbm_GBps"] / mp["hbm_GBps"]
             ent["bound"] = "hbm"
         paths[name] = ent
     line["paths"] = paths
+    if mp:
+        line["roofline"]["frac_of_measured_peak"] = achieved / mp["f32_TFLOPs"]
     if "f16" in paths and "f32" in paths:
         line["fp16_mfma_vs_fp32_speedup"] = paths["f16"]["beam_samples_per_s"] / paths["f32"]["beam_samples_per_s"]
     if extra:

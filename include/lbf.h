@@ -171,6 +171,23 @@ int lbf_transpose(const void* d_in, int C2, int B, int T2, int K, int elem_bytes
 int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product, int t_int,
                    int f_int, float* d_out, void* stream);
 
+/*
+ * Peak probes, for reporting the kernels' rooflines against what this device
+ * sustains beside the datasheet figures (not part of the beam former).
+ *   kind 0: a register-only loop of MFMA 32x32x16 f16 (the FP16 contraction's
+ *           instruction), two 256-thread work groups per compute unit,
+ *           `iters` iterations of 8 independent MFMAs per wave; *work = flop.
+ *   kind 1: the same with MFMA 32x32x2 f32; *work = flop.
+ *   kind 2: a 16-byte copy of `bytes` (rounded down to 16) from d_src to
+ *           d_dst (device buffers, not overlapping); *work = bytes moved
+ *           (read + write).
+ * d_dst must be a device buffer of at least 1024 bytes for kinds 0 and 1 (it
+ * is never written).  The caller times the call with events on `stream`.
+ * Errors: LBF_E_INVAL for an unknown kind, iters < 1, NULL pointers or
+ * bytes < 16 for a copy.
+ */
+int lbf_probe(int kind, int iters, const void* d_src, void* d_dst, uint64_t bytes, double* work, void* stream);
+
 /* Bytes of each operand of a block (host arithmetic, no device access). */
 typedef struct {
     uint64_t input_bytes, weight_bytes, output_bytes;

@@ -235,6 +235,16 @@ int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product,
     return ok();
 }
 
+int lbf_probe(int kind, int iters, const void* d_src, void* d_dst, uint64_t bytes, double* work, void* stream) {
+    if (!work || !d_dst) return fail(LBF_E_INVAL, "lbf_probe: NULL pointer");
+    if (kind < 0 || kind > 2) return fail(LBF_E_INVAL, "lbf_probe: unknown kind %d", kind);
+    if (kind < 2 && iters < 1) return fail(LBF_E_INVAL, "lbf_probe: iters must be >= 1");
+    if (kind == 2 && (!d_src || bytes < 16)) return fail(LBF_E_INVAL, "lbf_probe: copy needs a source and >= 16 bytes");
+    hipError_t e = lbf::launch_probe(kind, iters, d_src, d_dst, (size_t)bytes, work, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_probe");
+    return LBF_OK;
+}
+
 int lbf_block_footprint(const lbf_block* b, lbf_block_sizes* out) {
     if (!out) return fail(LBF_E_INVAL, "lbf_block_footprint: out is NULL");
     if (!b) return fail(LBF_E_INVAL, "lbf_block_footprint: block is NULL");

@@ -23,6 +23,7 @@ hipError_t launch_stokes(const float* y, int B, int C, int T, int product, int t
                          hipStream_t st);
 hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int elem_bytes, void* out,
                             hipStream_t st);
+hipError_t launch_probe(int kind, int iters, const void* src, void* dst, size_t bytes, double* work, hipStream_t st);
 hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, int ldb, float* out, hipStream_t st);
 hipError_t launch_incoherent(const void* x, int xtype, int S, int C, int T, int product, int t_int, int f_int,
                              float* out, hipStream_t st);

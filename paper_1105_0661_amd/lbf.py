@@ -94,6 +94,8 @@ _PROTOS = {
     "lbf_incoherent": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_block_footprint": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.POINTER(BlockSizes)]),
+    "lbf_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "lbf_server_create": (ctypes.c_int, [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
     "lbf_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]),
     "lbf_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(JobStatus)]),
@@ -323,6 +325,19 @@ def block_footprint(S: int, C: int, T: int, B: int, xtype: int, ctype: int, prod
 # --------------------------------------------------------------------------
 # streaming server
 # --------------------------------------------------------------------------
+
+PROBE_MFMA_F16, PROBE_MFMA_F32, PROBE_COPY = 0, 1, 2
+
+
+def probe(kind: int, iters: int = 1, src=None, dst=None, stream=None) -> float:
+    """lbf_probe: launch one peak probe on the stream; returns its work (flop,
+    or bytes moved for the copy).  The caller times it."""
+    work = ctypes.c_double()
+    nbytes = 0 if src is None else src.numel() * src.element_size()
+    _check(lib().lbf_probe(kind, iters, _dev_ptr(src, "src"), _dev_ptr(dst, "dst"), nbytes, ctypes.byref(work),
+                           _stream(stream)))
+    return work.value
+
 
 class Server:
     """lbf_server_* over a caller-owned device arena (a torch uint8 tensor).
