@@ -321,12 +321,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_one_second_fp32.txt")
 
 
 def kernel_source_hash():
-    """sha256 over the sources of the FP32 contraction kernel."""
+    """sha256 over the code of the FP32 contraction kernel's sources: comments
+    and blank lines are dropped, so that only a change of code invalidates the
+    counter measurements."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1105_0661_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1105_0661_amd", "csrc", f)) as fh:
+            src = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in src.splitlines()]
+        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

@@ -104,8 +104,13 @@ typedef struct {
 } lbf_block;
 
 /*
- * Run one block.  The Stokes products are fused: detection, integration and
- * the beam-major store happen in the epilogue of the contraction kernel.
+ * Run one block.  The Stokes products are fused: detection and integration
+ * happen in the epilogue of the contraction kernel.  Blocks of at most 64
+ * stations of complex int8/int16 with t_int <= 16 and no channel integration
+ * (the fast workers) form them channel-major in a staging buffer taken from
+ * the device's stream-ordered memory pool, then reorder them into the final
+ * order: the same two steps as lbf_beamform_channel_major + lbf_beam_major.
+ * Other blocks store the final order from the epilogue directly.
  * Errors: LBF_E_INVAL (sizes < 1, NULL pointers, T % t_int, C % f_int,
  * t_int/f_int != 1 for voltages, unknown enums); LBF_E_UNSUPPORTED for a Stokes
  * block whose t_int is not a power of two (use lbf_beamform with VOLTAGES,

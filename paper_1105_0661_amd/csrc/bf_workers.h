@@ -1,11 +1,16 @@
 // bf_workers.h -- the per-work-item contraction workers.
 //
-// Work item = (channel group of f_int channels, group of up to 128 beams).
-// A work group of 4 waves stages that beam group's weights for one channel in
-// LDS; each wave walks its own 32-sample tiles (groups of tiles when t_int >=
-// 32), streaming station samples from HBM straight into MFMA operand registers
-// (int -> f32/f16/bf16 in registers, no separate conversion pass), and ends
-// each tile with the fused Stokes / integration / beam-major store epilogue.
+// Fast workers (up to 64 stations of complex int8/int16, t_int <= 16, no
+// channel integration): item_f32_fast and item_h_fast, described where they
+// are defined; they write Stokes products channel-major.
+//
+// Generic workers (any station count, complex float input, channel
+// integration, t_int >= 32): work item = (channel group of f_int channels,
+// group of up to 128 beams).  A work group of 4 waves stages that beam group's
+// weights for one channel in LDS; each wave walks its own 32-sample tiles
+// (groups of tiles when t_int >= 32), streaming station samples from HBM
+// straight into MFMA operand registers, and ends each tile with the fused
+// Stokes / integration / store epilogue in either output order.
 #pragma once
 #include <type_traits>
 
