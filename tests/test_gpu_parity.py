@@ -373,3 +373,24 @@ def test_precision_block_sampled(ctype):
     ev = relerr(cplx(y), yo)
     flush("  voltage rel err %s: %.3g" % (CT_NAMES[ctype], ev))
     assert ev <= 3e-3
+
+
+# --------------------------------------------------------------------------
+# peak probes
+# --------------------------------------------------------------------------
+
+def test_probe_copy_is_a_copy_and_mfma_probes_report_their_work():
+    torch = _torch()
+    src = torch.arange(1 << 20, dtype=torch.float32, device="cuda:0")
+    dst = torch.zeros_like(src)
+    work = lbf.probe(lbf.PROBE_COPY, 1, src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    assert work == 2 * src.numel() * 4
+    sink = torch.zeros(512, dtype=torch.float32, device="cuda:0")
+    for kind, flop in ((lbf.PROBE_MFMA_F16, 32768), (lbf.PROBE_MFMA_F32, 4096)):
+        w = lbf.probe(kind, 3, None, sink)
+        torch.cuda.synchronize()
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        assert w == 2 * cus * 4 * 3 * 8 * flop
+    assert torch.count_nonzero(sink).item() == 0          # the probes never write their sink

@@ -166,10 +166,13 @@ def test_queue_status_codes():
 STREAM_CUTS = [0, 100, 110, 184, 256]
 
 
-@pytest.mark.parametrize("ctype", [lbf.F16, lbf.F32], ids=["f16", "f32"])
-def test_stream_carry_equals_the_concatenated_block(ctype):
+@pytest.mark.parametrize("ctype,prod,t_int,f_int,periods", [
+    (lbf.F16, lbf.STOKES_IQUV, 16, 1, [6, 0, 5, 5]),
+    (lbf.F32, lbf.STOKES_IQUV, 16, 1, [6, 0, 5, 5]),
+    (lbf.BF16, lbf.STOKES_I, 8, 2, [12, 1, 10, 9]),       # channel integration: the generic workers
+], ids=["f16", "f32", "bf16-I-t8-f2"])
+def test_stream_carry_equals_the_concatenated_block(ctype, prod, t_int, f_int, periods):
     torch = _torch()
-    t_int, prod = 16, lbf.STOKES_IQUV
     streams = [synth.make_block(24, 17, 2, 16, 256, "ci8", 16.0, tag=(1105, 661, 90)),
                synth.make_block(40, 9, 1, 8, 256, "ci16", 40.0, tag=(1105, 661, 91))]
     xs = [to_dev(b.x) for b in streams]
@@ -182,7 +185,7 @@ def test_stream_carry_equals_the_concatenated_block(ctype):
             for i, (blk, x) in enumerate(zip(streams, xs)):
                 flush("server stream %d samples [%d, %d) %s" % (i, a, b, CT_NAMES[ctype]))
                 tickets[i].append(srv.submit(300 + i, blk.station_xyz, blk.beam_dir, blk.freq_hz,
-                                             x[:, :, a:b].contiguous(), ctype, prod, t_int, 1,
+                                             x[:, :, a:b].contiguous(), ctype, prod, t_int, f_int,
                                              ref_dir=blk.ref_dir, stream_id=7 + i))
             t_plain = _submit(srv, plain, prod, 16, 1, 310, ctype, to_dev(plain.x))
             assert srv.wait(t_plain).state == lbf.JOB_DONE
@@ -193,10 +196,10 @@ def test_stream_carry_equals_the_concatenated_block(ctype):
                 assert st.state == lbf.JOB_DONE, (st.state, st.error)
                 assert st.periods == srv.output(t).shape[2]
                 outs.append(srv.output(t).clone())
-            assert [o.shape[2] for o in outs] == [6, 0, 5, 5]
+            assert [o.shape[2] for o in outs] == periods
             got = torch.cat(outs, dim=2)
             torch.cuda.synchronize()
-            ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, t_int, 1, 8)
+            ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, t_int, f_int, 8)
             g = got.cpu().numpy()
             assert g.shape == ref.shape
             for k in range(ref.shape[1]):
