@@ -122,7 +122,8 @@ int lbf_beamform(const lbf_block* blk, void* stream);
  * The same block with the Stokes products left channel-major, the order in
  * which they are formed (each channel's beams together, Section 4.3), before
  * the reorder into the final order (Section 4.6):
- *   d_out  STOKES: f32 [C'][K][T'][B] (beams fastest);  VOLTAGES: as lbf_beamform.
+ *   d_out  STOKES: f32 [C'][T'][B][K] (each beam's K parameters together, then
+ *          the beams);  VOLTAGES: as lbf_beamform.
  * lbf_beam_major of this output equals lbf_beamform's output bit for bit.
  * Errors: as lbf_beamform.
  */
@@ -130,7 +131,7 @@ int lbf_beamform_channel_major(const lbf_block* blk, void* stream);
 
 /*
  * Reorder channel-major Stokes into the final per-beam order (Section 4.6):
- *   out[b][k][t][c] = in[c][k][t][b],   in f32 [C2][K][T2][B], out f32 [B][K][T2][C2].
+ *   out[b][k][t][c] = in[c][t][b][k],   in f32 [C2][T2][B][K], out f32 [B][K][T2][C2].
  * K = 1 or 4.  in and out must not overlap.  Exact (a permutation).
  * Errors: LBF_E_INVAL for sizes < 1, K not 1 or 4, NULL or overlapping buffers.
  */

@@ -79,7 +79,7 @@ lbf::BlockDesc to_desc(const lbf_block* b) {
     d.order = 0;
     d.b0 = 0;
     d.b1 = b->B;
-    d.ldb = b->B;
+    d.ld_row = b->B * (b->product == LBF_STOKES_IQUV ? 4 : 1);
     return d;
 }
 
@@ -166,7 +166,7 @@ int lbf_beam_major(const float* d_in, int C2, int K, int T2, int B, float* d_out
     if (a < b + bytes && b < a + bytes) return fail(LBF_E_INVAL, "lbf_beam_major: input and output overlap");
     if ((long long)K * T2 > 0x7fffffffLL || C2 > (1 << 26) || B > (1 << 26))
         return fail(LBF_E_INVAL, "lbf_beam_major: too large");
-    hipError_t e = lbf::launch_stage_to_beam_major(d_in, C2, K * T2, B, B, d_out, (hipStream_t)stream);
+    hipError_t e = lbf::launch_stage_to_beam_major(d_in, C2, T2, B * K, B * K, d_out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lbf_beam_major");
     return ok();
 }

@@ -288,8 +288,10 @@ hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int el
 }
 
 // ---------------------------------------------------------------------------
-// Beam-fastest staging s[c][m][b] (rows of ldb >= B beams) -> final order
-// out[b][m][c] (m = k*T' + t', Section 4.6).  Each work group moves a
+// Channel-major staging s[c][m][b] (rows of ldb >= B values) -> out[b][m][c]
+// (Section 4.6).  For Stokes the staging is [c][t'][beam][k]: m = t' and the
+// B index runs over (beam, k) pairs, so out[(beam k)][t'][c] is the final
+// [beam][k][t'][c].  Each work group moves a
 // 64-channel x 64-beam tile of one m through LDS: reads are 256-byte runs
 // along b, writes 256-byte runs along c, 16 bytes per lane where the rows allow
 // it (VEC: ldb and C2 multiples of 4).  With ldb a multiple of 32 every read

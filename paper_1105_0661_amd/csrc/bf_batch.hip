@@ -82,7 +82,7 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
         }
         const int K = blks[j].product == PR_IQUV ? 4 : 1;
         stage_off[nsrc] = stage_bytes;
-        stage_bytes += ((size_t)blks[j].C * K * (blks[j].T / blks[j].t_int) * staging_ldb(blks[j].B) * sizeof(float) +
+        stage_bytes += ((size_t)blks[j].C * (blks[j].T / blks[j].t_int) * staging_ld(blks[j].B, K) * sizeof(float) +
                         255) & ~(size_t)255;
         src[nsrc] = j;
         // a beam tail of at most 128 beams becomes an entry of its own while
@@ -105,7 +105,7 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
     for (int j = 0; j < a.n; ++j) {
         a.blk[j].out = stage + stage_off[entry_src[j]];
         a.blk[j].order = 1;
-        a.blk[j].ldb = staging_ldb(a.blk[j].B);
+        a.blk[j].ld_row = staging_ld(a.blk[j].B, a.blk[j].product == PR_IQUV ? 4 : 1);
         int nbg;
         const int items = block_items_fast_h(a.blk[j], &nbg);
         a.nbg[j] = nbg;
@@ -135,9 +135,8 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
     for (int j = 0; j < nsrc && e == hipSuccess; ++j) {
         const BlockDesc& b = blks[src[j]];
         const int K = b.product == PR_IQUV ? 4 : 1;
-        e = launch_stage_to_beam_major((const float*)(stage + stage_off[j]), b.C, K * (b.T / b.t_int), b.B,
-                                       staging_ldb(b.B),
-                                       (float*)b.out, st);
+        e = launch_stage_to_beam_major((const float*)(stage + stage_off[j]), b.C, b.T / b.t_int, b.B * K,
+                                       staging_ld(b.B, K), (float*)b.out, st);
     }
     const hipError_t ef = hipFreeAsync(stage, st);
     return e != hipSuccess ? e : ef;

@@ -521,11 +521,28 @@ LBF_INLINE __amdgpu_buffer_rsrc_t channel_rsrc(void* out, int c, uint32_t bytes_
                                              (int)bytes_per_channel, 0x00020000);
 }
 
-// Stokes of one 32x32 tile into channel-major s[k][t'][b] of its channel
+// The Stokes parameters of one (t', beam) into the channel-major s[t'][b][k]
+// of its channel (rows of ld floats per t'): one 16-byte store for IQUV.
+template <int PR>
+LBF_INLINE void stokes_store_row(const float (&v)[4], __amdgpu_buffer_rsrc_t rs, int ld, int tq, int beam, bool ok) {
+    if (PR == PR_IQUV) {
+        const uint32_t off = store_off(ok, ((uint32_t)tq * (uint32_t)ld + (uint32_t)beam * 4u) * 4u);
+        floatx4 w;
+        w[0] = v[0];
+        w[1] = v[1];
+        w[2] = v[2];
+        w[3] = v[3];
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, w), rs, (int)off, 0, 0);
+    } else {
+        const uint32_t off = store_off(ok, ((uint32_t)tq * (uint32_t)ld + (uint32_t)beam) * 4u);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), rs, (int)off, 0, 0);
+    }
+}
+
+// Stokes of one 32x32 tile into channel-major s[t'][b][k] of its channel
 template <int PR, int TI>
-LBF_INLINE void stokes_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t rs, int ldb, int T2, int beam, int t0,
+LBF_INLINE void stokes_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t rs, int ld, int T2, int beam, int t0,
                                 int h, bool ok) {
-    constexpr int K = PR == PR_IQUV ? 4 : 1;
     constexpr int NOUT = 16 / TI;
     const int tq0 = (t0 + 16 * h) / TI;
 #pragma unroll
@@ -534,12 +551,7 @@ LBF_INLINE void stokes_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t
         stokes_sums<PR, TI>(acc, o * TI, sm);
         stokes_from_sums<PR>(sm, v);
         const int tq = tq0 + o;
-        const bool st = ok && tq < T2;
-#pragma unroll
-        for (int kk = 0; kk < K; ++kk) {
-            const uint32_t off = store_off(st, (((uint32_t)kk * T2 + tq) * (uint32_t)ldb + beam) * 4u);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[kk]), rs, (int)off, 0, 0);
-        }
+        stokes_store_row<PR>(v, rs, ld, tq, beam, ok && tq < T2);
     }
 }
 
@@ -634,11 +646,11 @@ LBF_INLINE EpiCtx make_epi(const BlockDesc& d, int PR_, int g) {
         e.st = (size_t)e.C2;
         e.sk = (size_t)e.T2 * e.C2;
         e.sb = (size_t)e.K * e.T2 * e.C2;
-    } else {                     // [C'][K][T'][B]
-        e.sb = 1;
-        e.st = (size_t)d.ldb;
-        e.sk = (size_t)e.T2 * d.ldb;
-        e.sc = (size_t)e.K * e.T2 * d.ldb;
+    } else {                     // [C'][T'][B][K], rows of ld_row floats per t'
+        e.sk = 1;
+        e.sb = (size_t)e.K;
+        e.st = (size_t)d.ld_row;
+        e.sc = (size_t)e.T2 * d.ld_row;
     }
     return e;
 }
@@ -708,9 +720,10 @@ inline int block_items(const BlockDesc& d, int* nbg) {
     return ngroups_c * *nbg;
 }
 
-// Beams per row of the internal channel-major Stokes staging: a multiple of
-// 32 floats, so that every row starts on a 128-byte line
-__host__ __device__ constexpr int staging_ldb(int B) { return (B + 31) & ~31; }
+// Floats per (c', t') row of the internal channel-major Stokes staging (B
+// beams x K parameters): a multiple of 32, so that every row starts on a
+// 128-byte line
+__host__ __device__ constexpr int staging_ld(int B, int K) { return (B * K + 31) & ~31; }
 
 __host__ __device__ constexpr int sample_bytes(int xtype) { return xtype == XT_CI8 ? 4 : xtype == XT_CI16 ? 8 : 16; }
 
@@ -723,7 +736,7 @@ __host__ __device__ inline bool fast_path(const BlockDesc& d) {
     if (d.product != PR_VOLT && (d.t_int > 16 || d.f_int != 1)) return false;
     // one channel's output (addressed with 32-bit buffer offsets, 2^31 = "no store")
     const double out_ch = d.product == PR_VOLT ? 16.0 * d.B * (double)d.T
-                                               : 4.0 * d.product * staging_ldb(d.B) * (double)(d.T / d.t_int);
+                                               : 4.0 * staging_ld(d.B, d.product) * (double)(d.T / d.t_int);
     if (out_ch >= 2147483648.0 - 4096.0) return false;
     return 8.0 * (double)d.C * (double)d.T * sample_bytes(d.xtype) < 2147483648.0 - 4096.0;
 }

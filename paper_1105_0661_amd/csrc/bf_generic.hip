@@ -88,25 +88,26 @@ hipError_t staging_alloc(void** p, size_t bytes, hipStream_t st) {
 }
 
 // lbf_beamform: the fast workers where they apply, the generic ones otherwise.
-// The fast workers write Stokes products channel-major ([C'][K][T'][ldb],
-// beams fastest); a beam-major block (order 0) goes through a staging buffer of
-// that layout, rows padded to a multiple of 32 beams (stream-ordered
-// allocation), and a tiled transpose.
+// The fast workers write Stokes products channel-major ([C'][T'][B][K], one
+// 16-byte store per beam and period for IQUV); a beam-major block (order 0)
+// goes through a staging buffer of that layout, rows padded to a multiple of
+// 32 floats (stream-ordered allocation), and a tiled transpose.
 hipError_t launch_beamform(const BlockDesc& d, hipStream_t st) {
     if (!fast_path(d)) return launch_beamform_generic(d, st);
     if (d.product == PR_VOLT || d.order == 1) return launch_fast(d, st);
     const int K = d.product == PR_IQUV ? 4 : 1;
     const int T2 = d.T / d.t_int;
     void* stage = nullptr;
-    const int ldb = staging_ldb(d.B);
-    hipError_t e = staging_alloc(&stage, (size_t)d.C * K * T2 * ldb * sizeof(float), st);
+    const int ld = staging_ld(d.B, K);
+    hipError_t e = staging_alloc(&stage, (size_t)d.C * T2 * ld * sizeof(float), st);
     if (e != hipSuccess) return e;
     BlockDesc ds = d;
     ds.out = stage;
     ds.order = 1;
-    ds.ldb = ldb;
+    ds.ld_row = ld;
     e = launch_fast(ds, st);
-    if (e == hipSuccess) e = launch_stage_to_beam_major((const float*)stage, d.C, K * T2, d.B, ldb, (float*)d.out, st);
+    // [c][t'][b k] -> [b k][t'][c]: the beam-major final order [b][k][t'][c]
+    if (e == hipSuccess) e = launch_stage_to_beam_major((const float*)stage, d.C, T2, d.B * K, ld, (float*)d.out, st);
     const hipError_t ef = hipFreeAsync(stage, st);
     return e != hipSuccess ? e : ef;
 }

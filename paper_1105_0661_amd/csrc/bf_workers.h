@@ -64,7 +64,6 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
     typedef typename R::type RT;
     constexpr int BYTES = sizeof(RT);
     constexpr int NOUT = PR == PR_VOLT ? 1 : 16 / TI;
-    constexpr int K = PR == PR_IQUV ? 4 : 1;
     const int T = d.T, S = d.S, B = d.B;
     const int ntiles_all = (T + kTile - 1) / kTile;
     const int nseg = (ntiles_all + kSegTiles - 1) / kSegTiles;
@@ -85,7 +84,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
     const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
     const int T2 = PR == PR_VOLT ? T : T / TI;
     const __amdgpu_buffer_rsrc_t ors =
-        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)K * T2 * d.ldb * 4u);
+        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)T2 * d.ld_row * 4u);
     const int trow = tile_row_sample(r);
 
     stage_weights_f32_planes(pl, d, c, b0);
@@ -180,12 +179,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
                 float v[4];
                 stokes_from_sums<PR>(sm[o], v);
                 const int tq = tq0 + o;
-#pragma unroll
-                for (int kq = 0; kq < K; ++kq) {
-                    const uint32_t off =
-                        store_off(okprev && beam < B && tq < T2, (((uint32_t)kq * T2 + tq) * (uint32_t)d.ldb + beam) * 4u);
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[kq]), ors, (int)off, 0, 0);
-                }
+                stokes_store_row<PR>(v, ors, d.ld_row, tq, beam, okprev && beam < B && tq < T2);
             }
         }
     };
@@ -193,7 +187,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
         const int tile = tile_of(klast);
         const bool ok = klast >= 0 && beam < B;
         if (PR == PR_VOLT) volt_store_cm(prev, ors, T, beam, tile * kTile, h, ok);
-        else stokes_store_cm<PR, TI>(prev, ors, d.ldb, T2, beam, tile * kTile, h, ok);
+        else stokes_store_cm<PR, TI>(prev, ors, d.ld_row, T2, beam, tile * kTile, h, ok);
     };
 
     load_quad(0, 0, 0);
@@ -282,10 +276,9 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     const int beam = d.b0 + (bg * NBT + bt) * kTile + r;
     const int nsteps = (ntiles + NS - 1) / NS;
     const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
-    constexpr int K = PR == PR_IQUV ? 4 : 1;
     const int T2 = PR == PR_VOLT ? T : T / TI;
     const __amdgpu_buffer_rsrc_t ors =
-        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)K * T2 * d.ldb * 4u);
+        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)T2 * d.ld_row * 4u);
 
     // this wave's weights, both variants, all K-steps
     u32x4 wr[NK], wi[NK];
@@ -417,11 +410,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
                 float v[4];
                 stokes_from_sums<PR>(sm[o], v);
                 const int tq = tq0 + o;
-#pragma unroll
-                for (int kq = 0; kq < K; ++kq) {
-                    const uint32_t off = store_off(okprev && tq < T2, (((uint32_t)kq * T2 + tq) * (uint32_t)d.ldb + beam) * 4u);
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[kq]), ors, (int)off, 0, 0);
-                }
+                stokes_store_row<PR>(v, ors, d.ld_row, tq, beam, okprev && tq < T2);
             }
         }
         __syncthreads();
@@ -431,7 +420,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
         const int tile = tile_lo + sigma + NS * klast;
         const bool ok = klast >= 0 && tile < tile_lo + ntiles && beam < bend;
         if (PR == PR_VOLT) volt_store_cm(prev, ors, T, beam, tile * kTile, h, ok);
-        else stokes_store_cm<PR, TI>(prev, ors, d.ldb, T2, beam, tile * kTile, h, ok);
+        else stokes_store_cm<PR, TI>(prev, ors, d.ld_row, T2, beam, tile * kTile, h, ok);
     };
 
     load_chunks(0);

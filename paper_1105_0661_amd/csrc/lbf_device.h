@@ -31,7 +31,7 @@ struct BlockDesc {
     int t_int, f_int;
     int order;          // Stokes: 0 = [B][K][T'][C'] (beam-major), 1 = [C'][K][T'][B] (channel-major)
     int b0, b1;         // beams [b0, b1) taken by the fast FP16/BF16 worker (0, B for a whole block)
-    int ldb;            // Stokes order 1: beams per [C'][K][T'] row of the output (>= B)
+    int ld_row;         // Stokes order 1: floats per [C'][T'] row of [B][K] values (>= B*K)
 };
 
 // ---------------------------------------------------------------------------

@@ -189,7 +189,7 @@ def output_shape(product: int, S: int, C: int, T: int, B: int, t_int: int = 1, f
     if product == VOLTAGES:
         return (C, B, T, 2, 2)
     if channel_major:
-        return (C // f_int, n_stokes(product), T // t_int, B)
+        return (C // f_int, T // t_int, B, n_stokes(product))
     return (B, n_stokes(product), T // t_int, C // f_int)
 
 
@@ -235,7 +235,7 @@ def beamform(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, strea
 
 
 def beamform_channel_major(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, stream=None):
-    """As ``beamform`` but Stokes stay channel-major: [C'][K][T'][B] f32."""
+    """As ``beamform`` but Stokes stay channel-major: [C'][T'][B][K] f32."""
     torch = _torch()
     S, C, T = x.shape[0], x.shape[1], x.shape[2]
     B = w.shape[1]
@@ -248,9 +248,9 @@ def beamform_channel_major(x, w, product: int, t_int: int = 1, f_int: int = 1, o
 
 
 def beam_major(inp, out=None, stream=None):
-    """[C2][K][T2][B] f32 -> [B][K][T2][C2] (final order)."""
+    """[C2][T2][B][K] f32 -> [B][K][T2][C2] (final order)."""
     torch = _torch()
-    C2, K, T2, B = inp.shape
+    C2, T2, B, K = inp.shape
     if out is None:
         out = torch.empty((B, K, T2, C2), dtype=torch.float32, device=inp.device)
     _check(lib().lbf_beam_major(_dev_ptr(inp, "inp"), C2, K, T2, B, _dev_ptr(out, "out"), _stream(stream)))

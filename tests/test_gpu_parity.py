@@ -232,12 +232,13 @@ def test_channel_major_then_beam_major_equals_fused(ctype, S, product, t_int, f_
     blk = synth.make_block(S, 75, 2, 4, 128, xtype, 16.0 if xtype == "ci8" else 40.0, tag=(1105, 661, 65))
     flush("channel-major %s S=%d K=%d t_int=%d f_int=%d" % (CT_NAMES[ctype], S, product, t_int, f_int))
     x, w = to_dev(blk.x), _weights(blk, ctype)
-    cm = lbf.beamform_channel_major(x, w, product, t_int, f_int)      # [C'][K][T'][B]
+    cm = lbf.beamform_channel_major(x, w, product, t_int, f_int)      # [C'][T'][B][K]
     bm = lbf.beam_major(cm)
     fused = lbf.beamform(x, w, product, t_int, f_int)
     torch.cuda.synchronize()
-    assert cm.shape == (blk.C // f_int, product, blk.T // t_int, blk.B)
+    assert cm.shape == (blk.C // f_int, blk.T // t_int, blk.B, product)
     assert torch.equal(bm, fused)
+    assert torch.equal(bm, cm.permute(2, 3, 1, 0).contiguous())     # out[b][k][t][c] = cm[c][t][b][k]
     _check_stokes(bm.cpu().numpy(), _oracle_stokes(blk, product, t_int, f_int), TOL[ctype], "channel-major")
 
 
@@ -259,11 +260,11 @@ def test_long_block_is_cut_into_time_segments(ctype, B, xtype):
 def test_beam_major_reorder_is_exact():
     torch = _torch()
     g = torch.Generator(device="cuda:0").manual_seed(4)
-    for shape in [(37, 4, 9, 70), (1, 1, 1, 1), (65, 1, 3, 129), (3, 4, 300, 5)]:
+    for shape in [(37, 9, 70, 4), (1, 1, 1, 1), (65, 3, 129, 1), (3, 300, 5, 4)]:   # [C2][T2][B][K]
         a = torch.randn(shape, device="cuda:0", generator=g)
         o = lbf.beam_major(a)
         torch.cuda.synchronize()
-        assert torch.equal(o, a.permute(3, 1, 2, 0).contiguous()), shape
+        assert torch.equal(o, a.permute(2, 3, 1, 0).contiguous()), shape
     a = torch.randn((4, 4, 4, 4), device="cuda:0", generator=g)
     with pytest.raises(lbf.LbfError) as ei:
         lbf.beam_major(a, out=a)
