@@ -469,32 +469,6 @@ LBF_INLINE void epilogue_tile(const floatx16 (&acc)[4], const EpiCtx& e, int bea
     }
 }
 
-// Fast workers, Stokes: integrated parameters go to a beam-fastest staging
-// layout s[c][k][t'][b] (e.out, e.c = channel).  The 32 lanes of a lane half
-// hold 32 consecutive beams, so every store instruction writes two whole
-// 128-byte lines; the beam-major final order is produced by a separate tiled
-// transpose.  (Storing straight into [b][k][t'][c] scatters 4-byte writes
-// whose lines, a multiple of 2^19 bytes apart, all fall into one L2 set.)
-template <int PR, int TI>
-LBF_INLINE void stokes_store_bfast(const floatx16 (&acc)[4], const EpiCtx& e, int beam, int t0, int h) {
-    constexpr int K = PR == PR_IQUV ? 4 : 1;
-    constexpr int NOUT = 16 / TI;
-    const int tq0 = (t0 + 16 * h) / TI;
-    const bool bok = beam < e.B;
-    float* base = e.out + (size_t)e.c * K * e.T2 * (size_t)e.B + beam;
-#pragma unroll
-    for (int o = 0; o < NOUT; ++o) {
-        float s[4], v[4];
-        stokes_sums<PR, TI>(acc, o * TI, s);
-        stokes_from_sums<PR>(s, v);
-        const int tq = tq0 + o;
-        if (bok && tq < e.T2) {
-#pragma unroll
-            for (int kk = 0; kk < K; ++kk) base[((size_t)kk * e.T2 + tq) * e.B] = v[kk];
-        }
-    }
-}
-
 // Branch-free stores of the fast FP16/BF16 worker.  rs covers one channel of
 // the output; a lane with nothing to store (beam >= B, sample past the end,
 // no tile) uses an offset past the end of the buffer, which the hardware
@@ -568,18 +542,6 @@ LBF_INLINE void volt_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t r
         v[2] = acc[2][k];
         v[3] = acc[3][k];
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs, (int)off, 0, 0);
-    }
-}
-
-// fast workers: t_int fixed at compile time, f_int == 1
-template <int PR, int TI>
-LBF_INLINE void epilogue_tiles_fixed(const floatx16 (&acc)[kBeamTiles][4], const EpiCtx& e, int b0, int r, int t0,
-                                     int h) {
-#pragma unroll
-    for (int a = 0; a < kBeamTiles; ++a) {
-        if (PR == PR_VOLT) epilogue_tile<PR>(acc[a], e, b0 + a * kTile + r, t0, h);
-        else stokes_store_bfast<PR, TI>(acc[a], e, b0 + a * kTile + r, t0, h);
-        __builtin_amdgcn_sched_barrier(0);   // one beam tile's temporaries at a time
     }
 }
 

@@ -29,7 +29,7 @@ struct BlockDesc {
     int S, C, T, B;
     int xtype, ctype, product;
     int t_int, f_int;
-    int order;          // Stokes: 0 = [B][K][T'][C'] (beam-major), 1 = [C'][K][T'][B] (channel-major)
+    int order;          // Stokes: 0 = [B][K][T'][C'] (beam-major), 1 = [C'][T'][B][K] (channel-major)
     int b0, b1;         // beams [b0, b1) taken by the fast FP16/BF16 worker (0, B for a whole block)
     int ld_row;         // Stokes order 1: floats per [C'][T'] row of [B][K] values (>= B*K)
 };
