@@ -219,7 +219,7 @@ def batched(lbf, torch, jobs, steps, warmup):
     per_job = [run(lambda it=it: lbf.beamform(*it[:5], out=it[5])) for it in items]
     return {"workload": "12 concurrent one-second observations: stations U{24..64}, beams U{1..400}, "
                         "16/64/256 channels x U{8..64} subbands, ci8/ci16, Stokes I or IQUV x16, FP16 MFMA, "
-                        "one persistent launch",
+                        "one persistent launch per worker variant",
             "jobs": [{"S": j["spec"].S, "B": j["spec"].B, "C": int(j["x"].shape[1]), "T": j["spec"].T,
                       "xtype": j["spec"].xtype, "product": j["spec"].product, "ms_alone": pj}
                      for j, pj in zip(jobs, per_job)],

@@ -139,11 +139,17 @@ int lbf_beam_major(const float* d_in, int C2, int K, int T2, int B, float* d_out
 
 /*
  * Several independent blocks (Section 7: independent observations processed
- * in parallel) in ONE launch of a persistent kernel that pulls
- * (block, channel-group) work items from a device queue.  Each block's result
- * is bitwise identical to lbf_beamform on that block alone.  All blocks must
- * be Stokes products with ctype F16 or BF16.  n <= LBF_MAX_BATCH.
- * Errors: as lbf_beamform, per block; LBF_E_INVAL if n < 1 or n > LBF_MAX_BATCH.
+ * in parallel).  Blocks are grouped by worker variant (input type, product,
+ * station count class, beam width); each group runs as ONE launch of a
+ * persistent kernel that pulls (block, item) work items from a device queue,
+ * so the items of all blocks of a group share the machine.  Blocks outside
+ * the batch kernels' path (t_int other than 16, channel integration, more
+ * than 64 stations) run through their own launches.  All launches go to
+ * `stream`.  Each block's result is bitwise identical to lbf_beamform on that
+ * block alone.  All blocks must be Stokes products with one ctype, F16 or
+ * BF16.  n <= LBF_MAX_BATCH.
+ * Errors: as lbf_beamform, per block; LBF_E_INVAL if n < 1 or n > LBF_MAX_BATCH;
+ * LBF_E_UNSUPPORTED for voltages, F32 operands or mixed ctypes.
  */
 #define LBF_MAX_BATCH 32
 int lbf_beamform_batch(const lbf_block* blks, int n, void* stream);
@@ -206,7 +212,7 @@ int lbf_block_footprint(const lbf_block* blk, lbf_block_sizes* out);
  * Section 7: independent observations run in parallel as long as resources
  * allow).  Jobs are queued on the host, admitted when their device footprint
  * fits the caller's arena and an in-flight slot is free, and run on a pool of
- * HIP streams; several admitted jobs are fused into one persistent launch.
+ * HIP streams; several admitted jobs are batched as in lbf_beamform_batch.
  * Weights are cached on the device per observation id.                     */
 
 typedef struct lbf_server lbf_server;

@@ -1,11 +1,15 @@
-// bf_batch.hip -- one persistent launch over the work items of several
-// blocks (Section 7 of Mol & Romein: independent observations processed in
-// parallel while resources allow).  Work groups pull items from a device
-// counter; each item runs exactly the worker lbf_beamform would run for it,
-// so every block's result is bitwise the same alone or in a batch.  Blocks
-// outside the fast path (more than 64 stations, t_int other than 16, channel
-// integration, complex float input) are rare in a batch and run through their
-// own launches on the same stream.
+// bf_batch.hip -- persistent launches over the work items of several blocks
+// (Section 7 of Mol & Romein: independent observations processed in parallel
+// while resources allow).  The blocks are grouped by worker variant (input
+// type, product, K-steps, beam streams); one persistent launch per variant
+// present pulls that group's items from a device counter.  Each item runs
+// exactly the worker lbf_beamform would run for it, so every block's result is
+// bitwise the same alone or in a batch.  A kernel holding every variant at
+// once would carry the register needs of the largest and spill; one variant per
+// launch keeps the registers of the single-block kernels.  Blocks outside the
+// fast path (more than 64 stations, t_int other than 16, channel integration,
+// complex float input) are rare in a batch and run through their own launches
+// on the same stream.
 #include "bf_common.h"
 #include "bf_workers.h"
 
@@ -23,23 +27,18 @@ static_assert(sizeof(BatchArgs) <= 4096, "kernel argument block");
 // workers; everything else in a batch runs the generic ones.
 __host__ __device__ inline bool batch_fast(const BlockDesc& d) { return fast_path(d) && d.t_int == 16; }
 
-template <int XT, int CT, int PR>
-LBF_INLINE void batch_item_fast(const BlockDesc& d, int item, int nbg, uint32_t* at) {
+// variant index of a fast block: ((xtype, product), K-steps, streams)
+constexpr int kBatchVariants = 2 * 2 * 3 * 2;
+inline int batch_variant(const BlockDesc& d) {
     const int nk = fast_h_ksteps(d.S);
-    if (fast_h_streams(d) == 1) {
-        if (nk == 4) item_h_fast<XT, CT, PR, 16, 4, 1>(d, item, nbg, at);
-        else if (nk == 6) item_h_fast<XT, CT, PR, 16, 6, 1>(d, item, nbg, at);
-        else item_h_fast<XT, CT, PR, 16, 8, 1>(d, item, nbg, at);
-    } else {
-        if (nk == 4) item_h_fast<XT, CT, PR, 16, 4, 2>(d, item, nbg, at);
-        else if (nk == 6) item_h_fast<XT, CT, PR, 16, 6, 2>(d, item, nbg, at);
-        else item_h_fast<XT, CT, PR, 16, 8, 2>(d, item, nbg, at);
-    }
+    const int ik = nk == 4 ? 0 : nk == 6 ? 1 : 2;
+    const int xp = (d.xtype == XT_CI8 ? 0 : 2) + (d.product == PR_I ? 0 : 1);
+    return (xp * 3 + ik) * 2 + (fast_h_streams(d) - 1);
 }
 
-template <int CT>
+template <int XT, int CT, int PR, int NK, int NS>
 __global__ __launch_bounds__(kThreadsH) void bf_batch_kernel(BatchArgs a, int* counter) {
-    __shared__ __attribute__((aligned(16))) uint32_t at[2 * 2 * kATileWords];
+    __shared__ __attribute__((aligned(16))) uint32_t at[NS * 2 * kATileWords];
     __shared__ int next;
     const int total = a.item_start[a.n];
     for (;;) {
@@ -50,21 +49,54 @@ __global__ __launch_bounds__(kThreadsH) void bf_batch_kernel(BatchArgs a, int* c
         if (it >= total) break;     // every work group leaves once the list is exhausted
         int j = 0;
         while (j + 1 < a.n && a.item_start[j + 1] <= it) ++j;
-        const BlockDesc& d = a.blk[j];
-        const int item = it - a.item_start[j];
-        if (d.xtype == XT_CI8) {
-            if (d.product == PR_I) batch_item_fast<XT_CI8, CT, PR_I>(d, item, a.nbg[j], at);
-            else batch_item_fast<XT_CI8, CT, PR_IQUV>(d, item, a.nbg[j], at);
-        } else {
-            if (d.product == PR_I) batch_item_fast<XT_CI16, CT, PR_I>(d, item, a.nbg[j], at);
-            else batch_item_fast<XT_CI16, CT, PR_IQUV>(d, item, a.nbg[j], at);
-        }
+        item_h_fast<XT, CT, PR, 16, NK, NS>(a.blk[j], it - a.item_start[j], a.nbg[j], at);
     }
 }
 
 __global__ void fill_int_kernel(int* p, int n, int v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// One persistent launch of variant <XT, CT, PR, NK, NS>: one resident work
+// group per slot the hardware offers; the queue, not the grid, spreads the
+// uneven items.
+template <int XT, int CT, int PR, int NK, int NS>
+hipError_t launch_batch_k(const BatchArgs& a, int* counter, hipStream_t st) {
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bf_batch_kernel<XT, CT, PR, NK, NS>, kThreadsH, 0);
+    if (per_cu < 1) per_cu = 1;
+    const int total = a.item_start[a.n];
+    const int slots = cus * per_cu;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, st, counter, 1, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((bf_batch_kernel<XT, CT, PR, NK, NS>), dim3(total < slots ? total : slots), dim3(kThreadsH), 0,
+                       st, a, counter);
+    return hipGetLastError();
+}
+
+template <int XT, int CT, int PR>
+hipError_t launch_batch_pr(int v, const BatchArgs& a, int* counter, hipStream_t st) {
+    switch (v % 6) {
+        case 0: return launch_batch_k<XT, CT, PR, 4, 1>(a, counter, st);
+        case 1: return launch_batch_k<XT, CT, PR, 4, 2>(a, counter, st);
+        case 2: return launch_batch_k<XT, CT, PR, 6, 1>(a, counter, st);
+        case 3: return launch_batch_k<XT, CT, PR, 6, 2>(a, counter, st);
+        case 4: return launch_batch_k<XT, CT, PR, 8, 1>(a, counter, st);
+        default: return launch_batch_k<XT, CT, PR, 8, 2>(a, counter, st);
+    }
+}
+
+template <int CT>
+hipError_t launch_batch_variant(int v, const BatchArgs& a, int* counter, hipStream_t st) {
+    switch (v / 6) {
+        case 0: return launch_batch_pr<XT_CI8, CT, PR_I>(v, a, counter, st);
+        case 1: return launch_batch_pr<XT_CI8, CT, PR_IQUV>(v, a, counter, st);
+        case 2: return launch_batch_pr<XT_CI16, CT, PR_I>(v, a, counter, st);
+        default: return launch_batch_pr<XT_CI16, CT, PR_IQUV>(v, a, counter, st);
+    }
 }
 
 hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, hipStream_t st) {
@@ -111,26 +143,22 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
         a.nbg[j] = nbg;
         a.item_start[j + 1] = a.item_start[j] + items;
     }
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, st, d_counter, 1, 0);
-    e = hipGetLastError();
-    if (e == hipSuccess) {
-        // one resident work group per slot the hardware offers: the queue, not
-        // the grid, spreads the uneven items
-        int dev = 0, cus = 256, per_cu = 1;
-        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (a.blk[0].ctype == CT_F16)
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bf_batch_kernel<CT_F16>, kThreadsH, 0);
-        else
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bf_batch_kernel<CT_BF16>, kThreadsH, 0);
-        if (per_cu < 1) per_cu = 1;
-        const int total = a.item_start[a.n];
-        const int slots = cus * per_cu;
-        const int grid = total < slots ? total : slots;
-        if (a.blk[0].ctype == CT_F16)
-            hipLaunchKernelGGL(bf_batch_kernel<CT_F16>, dim3(grid), dim3(kThreadsH), 0, st, a, d_counter);
-        else
-            hipLaunchKernelGGL(bf_batch_kernel<CT_BF16>, dim3(grid), dim3(kThreadsH), 0, st, a, d_counter);
-        e = hipGetLastError();
+    // one launch per variant present, in variant order, on the same stream;
+    // the counter is reset before each
+    for (int v = 0; v < kBatchVariants && e == hipSuccess; ++v) {
+        BatchArgs g;
+        g.n = 0;
+        g.item_start[0] = 0;
+        for (int j = 0; j < a.n; ++j) {
+            if (batch_variant(a.blk[j]) != v) continue;
+            g.blk[g.n] = a.blk[j];
+            g.nbg[g.n] = a.nbg[j];
+            g.item_start[g.n + 1] = g.item_start[g.n] + (a.item_start[j + 1] - a.item_start[j]);
+            g.n++;
+        }
+        if (g.n == 0) continue;
+        e = a.blk[0].ctype == CT_F16 ? launch_batch_variant<CT_F16>(v, g, d_counter, st)
+                                     : launch_batch_variant<CT_BF16>(v, g, d_counter, st);
     }
     for (int j = 0; j < nsrc && e == hipSuccess; ++j) {
         const BlockDesc& b = blks[src[j]];

@@ -295,7 +295,7 @@ def test_incoherent_beam_matches_oracle():
 
 
 # --------------------------------------------------------------------------
-# batches: one persistent launch == separate launches, bit for bit
+# batches: persistent launches per worker variant == separate launches, bit for bit
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("ctype", [lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
@@ -303,12 +303,13 @@ def test_batch_equals_single_launches_bitwise(ctype):
     torch = _torch()
     # batch-kernel blocks (t_int 16, no channel integration): one and two
     # sample streams (more / at most 128 beams), 4, 6 and 8 K-steps, ragged
-    # T, a beam tail split off a 256-beam group; the rest run through their
-    # own launches
+    # T, a beam tail split off a 256-beam group, two blocks of one worker
+    # variant in one launch; the rest run through their own launches
     specs = [(24, 17, 2, 4, 64, "ci8", lbf.STOKES_I, 16, 1), (29, 130, 2, 3, 208, "ci8", lbf.STOKES_IQUV, 16, 1),
              (33, 200, 1, 4, 112, "ci16", lbf.STOKES_I, 16, 1), (64, 40, 2, 4, 176, "ci16", lbf.STOKES_IQUV, 16, 1),
              (40, 150, 1, 8, 96, "ci16", lbf.STOKES_IQUV, 16, 2), (45, 300, 1, 3, 64, "ci8", lbf.STOKES_IQUV, 16, 1),
-             (64, 33, 3, 2, 32, "ci8", lbf.STOKES_IQUV, 32, 1), (31, 1, 1, 5, 48, "ci16", lbf.STOKES_I, 4, 1)]
+             (64, 33, 3, 2, 32, "ci8", lbf.STOKES_IQUV, 32, 1), (31, 1, 1, 5, 48, "ci16", lbf.STOKES_I, 4, 1),
+             (26, 20, 1, 3, 80, "ci8", lbf.STOKES_I, 16, 1)]
     items, singles, refs = [], [], []
     for i, (S, B, nsb, nch, T, xt, prod, ti, fi) in enumerate(specs):
         blk = synth.make_block(S, B, nsb, nch, T, xt, 16.0 if xt == "ci8" else 40.0, tag=(1105, 661, 60 + i))

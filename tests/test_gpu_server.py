@@ -70,7 +70,7 @@ def test_results_alone_equal_results_in_the_mix(ctype):
         assert all(s.state == lbf.JOB_DONE for s in sts), [(s.state, s.error) for s in sts]
         mixed = [srv.output(t).clone() for t in tickets]
         if ctype != lbf.F32:
-            assert max(s.batch_size for s in sts) > 1      # admitted together, one persistent launch
+            assert max(s.batch_size for s in sts) > 1      # admitted together, batched
         for s in sts:
             assert s.t_submit_ns <= s.t_admit_ns <= s.t_start_ns <= s.t_done_ns
     torch.cuda.synchronize()
