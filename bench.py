@@ -139,6 +139,31 @@ def unfused(lbf, torch, x, geo, nch, steps, warmup):
             "rel_err_vs_fused": err}
 
 
+def incoherent(lbf, torch, x, steps, warmup, mp):
+    """The incoherent beam (sum over stations of the station powers) of the
+    whole one-second block, Stokes IQUV integrated x16: an HBM-bound read of
+    every sample once.  HIP events on the current stream around each launch."""
+    S, C, T = x.shape[:3]
+    n = warmup + steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n)]
+    out = None
+    for i in range(n):
+        ev[i][0].record()
+        out = lbf.incoherent(x, lbf.STOKES_IQUV, 16, 1, out=out)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(warmup, n)]))
+    nbytes = S * C * T * x.element_size() * 4 + 4 * (T // 16) * C * 4
+    gbps = nbytes / (ms / 1e3) / 1e9
+    r = {"workload": "incoherent beam of the one-second block (64 stations, 8192 channels, 768 samples, "
+                     "complex int16), Stokes IQUV x16",
+         "kernel_ms": ms, "algorithmic_bytes": nbytes, "hbm_GBps": gbps, "bound": "hbm",
+         "frac": gbps / PEAK["hbm_GBps"]}
+    if mp:
+        r["frac_of_measured_copy"] = gbps / mp["hbm_GBps"]
+    return r
+
+
 def measured_peaks(lbf, torch, dev):
     """What this device sustains: register-only MFMA loops in the contraction's
     instruction forms (FP16 32x32x16, FP32 32x32x2) and a 4 GiB device copy,
@@ -447,10 +472,12 @@ def main():
 
     # ---------------- the 488-beam precision block (MFMA-bound) ----------------
     extra = None
-    batch_res = serve_res = unfused_res = None
+    batch_res = serve_res = unfused_res = inc_res = None
     if not a.no_extra and not only:
         unfused_res = unfused(lbf, torch, x, geo, 1024, max(3, a.steps // 4), 1)
         log("unfused chain: %s" % unfused_res)
+        inc_res = incoherent(lbf, torch, x, max(5, a.steps // 2), a.warmup, mp)
+        log("incoherent beam: %s" % inc_res)
         b2 = synth.config2(threads=16)
         x2 = torch.from_numpy(b2.x).to(dev)
         geo2 = (torch.from_numpy(b2.station_xyz).to(dev), torch.from_numpy(b2.beam_dir).to(dev),
@@ -549,6 +576,8 @@ def main():
         line["precision_block"] = extra
     if unfused_res:
         line["unfused_chain"] = unfused_res
+    if inc_res:
+        line["incoherent_beam"] = inc_res
     if batch_res:
         line["batched"] = batch_res
     if serve_res:

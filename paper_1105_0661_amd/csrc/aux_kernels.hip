@@ -363,9 +363,8 @@ hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, 
 
 // ---------------------------------------------------------------------------
 // Incoherent beam (Section 3): sum over stations of each station's Stokes
-// parameters, integrated like a tied-array beam.  One thread per output
-// (c', t'); loops channel, time, station; reads are along t for a station.
-// out [K][T'][C'].
+// parameters, integrated like a tied-array beam.  out [K][T'][C'].
+// Generic form: one thread per output (c', t'); loops channel, time, station.
 // ---------------------------------------------------------------------------
 template <int XT, int K>
 __global__ __launch_bounds__(256) void incoherent_kernel(const void* __restrict__ x, int S, int C, int T, int t_int,
@@ -394,8 +393,168 @@ __global__ __launch_bounds__(256) void incoherent_kernel(const void* __restrict_
     }
 }
 
+// Fast form, HBM-bound: one wave per (channel group c', run of 64 P samples),
+// P = 16 / sample bytes, so each lane reads one 16-byte vector of P
+// consecutive samples per station and channel; a wave's load covers 1 KiB of
+// one (station, channel) row.  Per sample the lane sums |X|^2, |Y|^2 and
+// X conj(Y) over stations and the f_int channels, then forms I, Q, U, V.
+// t_int is a power of two dividing 64 P, so a period never leaves a wave's
+// run: t_int <= P periods lie in one lane, longer ones span G = t_int / P
+// lanes and are summed with an xor butterfly.
+template <int XT> struct Vec16;
+template <> struct Vec16<XT_CI8> {
+    static constexpr int P = 4;
+    __device__ static inline void decode(const intx4 v, float (*f)[4]) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            f[p][0] = (float)((v[p] << 24) >> 24);
+            f[p][1] = (float)((v[p] << 16) >> 24);
+            f[p][2] = (float)((v[p] << 8) >> 24);
+            f[p][3] = (float)(v[p] >> 24);
+        }
+    }
+};
+template <> struct Vec16<XT_CI16> {
+    static constexpr int P = 2;
+    __device__ static inline void decode(const intx4 v, float (*f)[4]) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            f[p][0] = (float)((v[2 * p] << 16) >> 16);
+            f[p][1] = (float)(v[2 * p] >> 16);
+            f[p][2] = (float)((v[2 * p + 1] << 16) >> 16);
+            f[p][3] = (float)(v[2 * p + 1] >> 16);
+        }
+    }
+};
+template <> struct Vec16<XT_CF32> {
+    static constexpr int P = 1;
+    __device__ static inline void decode(const intx4 v, float (*f)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) f[0][q] = __int_as_float(v[q]);
+    }
+};
+
+// per-sample sums: a[0] |X|^2, a[1] |Y|^2, a[2] Re X conj Y, a[3] Im X conj Y
+__device__ __forceinline__ void power_acc(const float* v, float* a) {
+    a[0] = __builtin_fmaf(v[0], v[0], __builtin_fmaf(v[1], v[1], a[0]));
+    a[1] = __builtin_fmaf(v[2], v[2], __builtin_fmaf(v[3], v[3], a[1]));
+    a[2] = __builtin_fmaf(v[0], v[2], __builtin_fmaf(v[1], v[3], a[2]));
+    a[3] = __builtin_fmaf(v[1], v[2], __builtin_fmaf(-v[0], v[3], a[3]));
+}
+
+template <int XT, int K>
+__global__ __launch_bounds__(256) void incoherent_wave_kernel(const void* __restrict__ x, int S, int C, int T,
+                                                              int t_int, int f_int, int nrun, float* __restrict__ out) {
+    constexpr int P = Vec16<XT>::P;
+    constexpr int SB = Sample<XT>::bytes;
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int C2 = C / f_int, T2 = T / t_int;
+    if (wave >= (long)C2 * nrun) return;   // whole waves only; the kernel has no barrier
+    const int c2 = (int)(wave / nrun);
+    const int t0 = (int)(wave - (long)c2 * nrun) * 64 * P + lane * P;
+    const size_t sstride = (size_t)C * T;   // samples between stations
+    float a[P][4];
+#pragma unroll
+    for (int p = 0; p < P; ++p) a[p][0] = a[p][1] = a[p][2] = a[p][3] = 0.f;
+    for (int dc = 0; dc < f_int; ++dc) {
+        const size_t row = (size_t)(c2 * f_int + dc) * T + t0;   // station 0
+        if (t0 + P <= T) {
+            const intx4* q = reinterpret_cast<const intx4*>(static_cast<const char*>(x) + row * SB);
+            const size_t qs = sstride * SB / 16;
+            int s = 0;
+            for (; s + 4 <= S; s += 4) {
+                intx4 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(q + (size_t)(s + u) * qs);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    float f[P][4];
+                    Vec16<XT>::decode(v[u], f);
+#pragma unroll
+                    for (int p = 0; p < P; ++p) power_acc(f[p], a[p]);
+                }
+            }
+            for (; s < S; ++s) {
+                float f[P][4];
+                Vec16<XT>::decode(__builtin_nontemporal_load(q + (size_t)s * qs), f);
+#pragma unroll
+                for (int p = 0; p < P; ++p) power_acc(f[p], a[p]);
+            }
+        } else {
+            // the row's ragged end: per-sample loads of the samples before T
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    if (t0 + p < T) {
+                        const floatx4 v = Sample<XT>::load(x, row + (size_t)s * sstride + p);
+                        const float f[4] = {v[0], v[1], v[2], v[3]};
+                        power_acc(f, a[p]);
+                    }
+        }
+    }
+    // Stokes per sample, then the period sums
+    float st[P][K];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        st[p][0] = a[p][0] + a[p][1];
+        if (K == 4) {
+            st[p][1] = a[p][0] - a[p][1];
+            st[p][2] = 2.f * a[p][2];
+            st[p][3] = 2.f * a[p][3];
+        }
+    }
+    if (t_int <= P) {
+        for (int j = 0; j * t_int < P; ++j) {
+            if (t0 + j * t_int >= T) break;
+            const int t2 = t0 / t_int + j;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                float v = 0.f;
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    if (p >= j * t_int && p < (j + 1) * t_int) v += st[p][k];
+                out[((size_t)k * T2 + t2) * C2 + c2] = v;
+            }
+        }
+    } else {
+        const int G = t_int / P;
+        float v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v[k] = 0.f;
+#pragma unroll
+            for (int p = 0; p < P; ++p) v[k] += st[p][k];
+            for (int o = 1; o < G; o <<= 1) v[k] += __shfl_xor(v[k], o, 64);
+        }
+        if ((lane & (G - 1)) == 0 && t0 < T) {
+            const int t2 = t0 / t_int;
+#pragma unroll
+            for (int k = 0; k < K; ++k) out[((size_t)k * T2 + t2) * C2 + c2] = v[k];
+        }
+    }
+}
+
 hipError_t launch_incoherent(const void* x, int xtype, int S, int C, int T, int product, int t_int, int f_int,
                              float* out, hipStream_t st) {
+    const int P = xtype == XT_CI8 ? 4 : xtype == XT_CI16 ? 2 : 1;
+    const bool pow2 = (t_int & (t_int - 1)) == 0 && t_int <= 64 * P;
+    const long nrun = (T + 64L * P - 1) / (64L * P);
+    const long waves = (long)(C / f_int) * nrun;
+    // 16-byte rows: every (station, channel) row starts on a 16-byte boundary
+    const bool vec = ((size_t)T * (16 / P)) % 16 == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    if (pow2 && vec && waves <= 0x7fffffffL * 4L) {
+        const dim3 g((unsigned)((waves + 3) / 4)), b(256);
+#define LBF_INCW(XTV)                                                                                            \
+    if (product == PR_IQUV)                                                                                      \
+        hipLaunchKernelGGL((incoherent_wave_kernel<XTV, 4>), g, b, 0, st, x, S, C, T, t_int, f_int, (int)nrun, out); \
+    else hipLaunchKernelGGL((incoherent_wave_kernel<XTV, 1>), g, b, 0, st, x, S, C, T, t_int, f_int, (int)nrun, out);
+        if (xtype == XT_CI8) { LBF_INCW(XT_CI8) }
+        else if (xtype == XT_CI16) { LBF_INCW(XT_CI16) }
+        else { LBF_INCW(XT_CF32) }
+#undef LBF_INCW
+        return hipGetLastError();
+    }
     const size_t n = (size_t)(C / f_int) * (T / t_int);
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;

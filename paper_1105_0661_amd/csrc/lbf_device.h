@@ -10,6 +10,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
 typedef char charx4 __attribute__((ext_vector_type(4)));
 
 enum { XT_CI8 = 0, XT_CI16 = 1, XT_CF32 = 2 };

@@ -282,15 +282,32 @@ def test_voltages_beam_major_order_matches_oracle():
     assert relerr(cplx(vb), ref) <= 1e-5
 
 
-def test_incoherent_beam_matches_oracle():
+# (S, nsb, nch, T, xtype, product, t_int, f_int): power-of-two periods inside
+# one lane, across lanes and across a whole wave's run, ragged row ends, 5
+# stations (not a multiple of the 4-station unroll); then integrations the
+# vector form does not take (t_int 12 and 3, rows of 24 bytes) and go through
+# the generic kernel
+INCOHERENT_CASES = [(7, 2, 4, 64, "ci16", lbf.STOKES_IQUV, 8, 2), (64, 2, 16, 768, "ci16", lbf.STOKES_IQUV, 16, 1),
+                    (5, 1, 6, 520, "ci8", lbf.STOKES_I, 8, 2), (3, 1, 3, 70, "cf32", lbf.STOKES_IQUV, 2, 1),
+                    (4, 1, 2, 12, "ci8", lbf.STOKES_IQUV, 1, 1), (9, 1, 3, 512, "ci8", lbf.STOKES_IQUV, 256, 3),
+                    (6, 1, 2, 256, "ci16", lbf.STOKES_I, 128, 1), (2, 1, 2, 128, "cf32", lbf.STOKES_IQUV, 64, 2),
+                    (8, 1, 4, 96, "ci16", lbf.STOKES_IQUV, 12, 2), (3, 1, 2, 6, "ci8", lbf.STOKES_IQUV, 3, 1)]
+
+
+@pytest.mark.parametrize("case", INCOHERENT_CASES, ids=lambda c: "S%d_C%d_T%d_%s_K%d_t%d_f%d" % (
+    c[0], c[1] * c[2], c[3], c[4], lbf.n_stokes(c[5]), c[6], c[7]))
+def test_incoherent_beam_matches_oracle(case):
     torch = _torch()
-    blk = synth.make_block(7, 1, 2, 4, 64, "ci16", 30.0, tag=(1105, 661, 58))
+    S, nsb, nch, T, xt, prod, ti, fi = case
+    blk = synth.make_block(S, 1, nsb, nch, T, xt, 16.0 if xt == "ci8" else 30.0, tag=(1105, 661, 58))
     x = to_dev(blk.x)
-    out = lbf.incoherent(x, lbf.STOKES_IQUV, 8, 2)
+    flush("incoherent %s" % (case,))
+    out = lbf.incoherent(x, prod, ti, fi)
     torch.cuda.synchronize()
-    ref = orc.incoherent(blk.x, 4, 8, 2)                        # [C'][T'][K]
+    K = lbf.n_stokes(prod)
+    ref = orc.incoherent(blk.x, K, ti, fi)                      # [C'][T'][K]
     got = out.cpu().numpy()                                      # [K][T'][C']
-    for k in range(4):
+    for k in range(K):
         assert relerr(got[k].T, ref[..., k]) <= 1e-5
 
 
