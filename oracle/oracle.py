@@ -3,7 +3,8 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this module.  The GPU library never calls it and shares
 no code with it.  The arithmetic lives in ``lbf_oracle.c`` (plain C, FP64);
-this file compiles it with gcc and marshals numpy arrays.
+this file compiles it with gcc and marshals numpy arrays.  Dedispersion alone
+is written here in numpy (complex128), with numpy's FFT as its FFT step.
 
 Definitions followed (Mol & Romein, "The LOFAR Beam Former"):
 
@@ -17,6 +18,9 @@ Definitions followed (Mol & Romein, "The LOFAR Beam Former"):
 * ``integrate``  -- sums over t_int samples and f_int channels (Sec. 3, Sec. 5.1)
 * ``reorder``    -- final per-beam, per-Stokes order [b][k][t'][c'] (Sec. 4.6)
 * ``incoherent`` -- sum over stations of per-station Stokes (Sec. 3)
+* ``dedisperse`` -- channel-level dedispersion (Sec. 4.4): per block of
+  n_fft samples a forward FFT, a product with the channel's precomputed
+  complex chirp weights, and a backward FFT; numpy's FFT is the FFT step
 
 Parity pins for every function are in ``tests/test_oracle_pins.py``; the
 absolute values of the beam former have no worked example in the paper, so
@@ -192,3 +196,23 @@ def pipeline(x: np.ndarray, pos, dirs, ref, freq, K: int, t_int: int = 1, f_int:
 def block_weights(blk, use_ref: bool = True) -> np.ndarray:
     """Weights of a synthetic block (complex128 [C][B][S])."""
     return weights(delays(blk.station_xyz, blk.beam_dir, blk.ref_dir if use_ref else None), blk.freq_hz)
+
+
+def dedisperse(y: np.ndarray, chirp: np.ndarray, n_fft: int) -> np.ndarray:
+    """Channel-level dedispersion (Sec. 4.4) of beam voltages y[C][B][T][2]
+    (complex): every polarisation's time series is cut into blocks of n_fft
+    consecutive samples; each block is Fourier transformed (forward sign
+    exp(-2 pi i j k / n_fft)), multiplied bin by bin with the channel's chirp
+    weights chirp[C][n_fft] (bin k at index k), and transformed back.  The
+    backward transform carries the 1/n_fft factor, so all-one weights give
+    the input back.  Returns complex128 [C][B][T][2]."""
+    y = np.asarray(y, dtype=np.complex128)
+    chirp = np.asarray(chirp, dtype=np.complex128)
+    C, B, T, P = y.shape
+    if T % n_fft or chirp.shape != (C, n_fft):
+        raise ValueError("T must be a multiple of n_fft and chirp must be [C][n_fft]")
+    blocks = y.reshape(C, B, T // n_fft, n_fft, P)
+    spec = np.fft.fft(blocks, axis=3)                       # forward, per block and polarisation
+    spec = spec * chirp[:, None, None, :, None]              # the channel's chirp, same for every beam
+    out = np.fft.ifft(spec, axis=3)                          # backward, with the 1/n_fft factor
+    return out.reshape(C, B, T, P)

@@ -9,6 +9,8 @@ Former: Implementation and Performance Analysis".
 import math
 import os
 
+import cmath
+
 import numpy as np
 import pytest
 
@@ -292,3 +294,61 @@ def test_channel_constants_match_paper():
     for k, (val, unit, tol) in rows.items():
         assert got[k] == pytest.approx(val * scale[unit], rel=tol), k
     assert synth.samples_per_block(1.0, 256) == 768
+
+
+# --------------------------------------------------------------------------
+# channel-level dedispersion (Sec. 4.4)
+# --------------------------------------------------------------------------
+
+def _dd_input(C, B, T, seed):
+    rng = np.random.default_rng([1105, 661, seed])
+    return rng.standard_normal((C, B, T, 2)) + 1j * rng.standard_normal((C, B, T, 2))
+
+
+def test_dedisperse_brute_force_dft():
+    """The definition written out with explicit sums (no FFT routine): forward
+    DFT with exp(-2 pi i j k / n), product with the weights, backward DFT with
+    exp(+2 pi i k t / n) / n."""
+    n, C, B = 8, 2, 1
+    y = _dd_input(C, B, 2 * n, 1)
+    rng = np.random.default_rng(7)
+    chirp = np.exp(2j * np.pi * rng.random((C, n))) * (0.5 + rng.random((C, n)))
+    got = orc.dedisperse(y, chirp, n)
+    for c in range(C):
+        for blk in range(2):
+            for p in range(2):
+                x = [y[c, 0, blk * n + j, p] for j in range(n)]
+                X = [sum(x[j] * cmath.exp(-2j * cmath.pi * j * k / n) for j in range(n)) for k in range(n)]
+                Z = [X[k] * chirp[c, k] for k in range(n)]
+                for t in range(n):
+                    z = sum(Z[k] * cmath.exp(2j * cmath.pi * k * t / n) for k in range(n)) / n
+                    assert abs(got[c, 0, blk * n + t, p] - z) < 1e-12
+
+
+def test_dedisperse_unit_weights_are_identity():
+    y = _dd_input(3, 2, 3 * 64, 2)
+    assert np.allclose(orc.dedisperse(y, np.ones((3, 64)), 64), y, rtol=0, atol=1e-12)
+
+
+def test_dedisperse_linear_phase_is_a_circular_shift_per_channel():
+    """Weights exp(-2 pi i k d_c / n) delay channel c by d_c samples, cyclically
+    inside each block: out[t] = in[(t - d_c) mod n] (shift theorem)."""
+    n, C, B = 64, 3, 2
+    y = _dd_input(C, B, 2 * n, 3)
+    d = [5, 0, 63]
+    k = np.arange(n)
+    chirp = np.stack([np.exp(-2j * np.pi * k * dc / n) for dc in d])
+    got = orc.dedisperse(y, chirp, n)
+    for c, dc in enumerate(d):
+        blocks = y[c].reshape(B, 2, n, 2)
+        want = np.roll(blocks, dc, axis=2).reshape(B, 2 * n, 2)
+        assert np.allclose(got[c], want, rtol=0, atol=1e-12)
+
+
+def test_dedisperse_unit_modulus_weights_keep_the_energy():
+    n = 512
+    y = _dd_input(2, 1, n, 4)
+    rng = np.random.default_rng(9)
+    chirp = np.exp(2j * np.pi * rng.random((2, n)))
+    out = orc.dedisperse(y, chirp, n)
+    assert abs(np.sum(np.abs(out) ** 2) / np.sum(np.abs(y) ** 2) - 1) < 1e-12
