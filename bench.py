@@ -164,6 +164,39 @@ def incoherent(lbf, torch, x, steps, warmup, mp):
     return r
 
 
+def dedispersion(lbf, torch, dev, steps, warmup, mp):
+    """Channel-level dedispersion at Table 1 case E's shape on one GPU's share
+    of the subbands: 32 subbands x 16 channels (12.2 kHz), 10 beams, three
+    4096-sample blocks (1.007 s), seeded Gaussian voltages and unit-modulus
+    chirp weights.  FFT, chirp product and inverse FFT in one kernel that
+    reads and writes every voltage once: HBM-bound."""
+    C, B, T, n = 512, 10, 3 * 4096, 4096
+    gen = torch.Generator().manual_seed(1105661)
+    y = (torch.randn((C, B, T, 2, 2), generator=gen) * 100.0).to(dev)
+    ph = torch.rand((C, n), generator=gen, dtype=torch.float64) * 2 * np.pi
+    h = torch.stack([torch.cos(ph), torch.sin(ph)], dim=-1).float().to(dev)
+    out = torch.empty_like(y)
+    nrep = warmup + steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(nrep)]
+    for i in range(nrep):
+        ev[i][0].record()
+        lbf.dedisperse(y, h, n, out=out)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(warmup, nrep)]))
+    nbytes = 2 * C * B * T * 16 + C * n * 8
+    gbps = nbytes / (ms / 1e3) / 1e9
+    r = {"workload": "channel-level dedispersion, Table 1 case E share: 512 channels of 12.2 kHz, 10 beams, "
+                     "3 blocks of 4096 samples, 2 pols, FP32 FFT -> chirp -> inverse FFT",
+         "kernel_ms": ms, "algorithmic_bytes": nbytes, "hbm_GBps": gbps, "bound": "hbm",
+         "frac": gbps / PEAK["hbm_GBps"],
+         "beam_samples_per_s": C * B * T / (ms / 1e3)}
+    if mp:
+        r["frac_of_measured_copy"] = gbps / mp["hbm_GBps"]
+    del y, h, out
+    return r
+
+
 def measured_peaks(lbf, torch, dev):
     """What this device sustains: register-only MFMA loops in the contraction's
     instruction forms (FP16 32x32x16, FP32 32x32x2) and a 4 GiB device copy,
@@ -472,12 +505,14 @@ def main():
 
     # ---------------- the 488-beam precision block (MFMA-bound) ----------------
     extra = None
-    batch_res = serve_res = unfused_res = inc_res = None
+    batch_res = serve_res = unfused_res = inc_res = dd_res = None
     if not a.no_extra and not only:
         unfused_res = unfused(lbf, torch, x, geo, 1024, max(3, a.steps // 4), 1)
         log("unfused chain: %s" % unfused_res)
         inc_res = incoherent(lbf, torch, x, max(5, a.steps // 2), a.warmup, mp)
         log("incoherent beam: %s" % inc_res)
+        dd_res = dedispersion(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp)
+        log("dedispersion: %s" % dd_res)
         b2 = synth.config2(threads=16)
         x2 = torch.from_numpy(b2.x).to(dev)
         geo2 = (torch.from_numpy(b2.station_xyz).to(dev), torch.from_numpy(b2.beam_dir).to(dev),
@@ -578,6 +613,8 @@ def main():
         line["unfused_chain"] = unfused_res
     if inc_res:
         line["incoherent_beam"] = inc_res
+    if dd_res:
+        line["dedispersion"] = dd_res
     if batch_res:
         line["batched"] = batch_res
     if serve_res:

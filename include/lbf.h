@@ -184,6 +184,26 @@ int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product,
                    int f_int, float* d_out, void* stream);
 
 /*
+ * Channel-level dedispersion (Section 4.4): each polarisation's beam voltages
+ * are cut into blocks of n_fft consecutive samples; each block is Fourier
+ * transformed (forward sign exp(-2 pi i j k / n_fft)), multiplied bin by bin
+ * with its channel's precomputed chirp weights, and transformed back with a
+ * 1/n_fft factor, so all-one weights return the input.
+ *   d_y     complex f32 [C][B][T][2]   (lbf_beamform VOLTAGES layout)
+ *   d_chirp complex f32 [C][n_fft]     (bin k at index k; the same for every beam)
+ *   d_out   complex f32 [C][B][T][2];  may equal d_y (in place), must not
+ *           otherwise overlap it
+ * n_fft is 8, 64, 512 or 4096 (the paper's 3 Hz subchannels of a 12 kHz
+ * channel); T must be a multiple of n_fft.  Device buffers, caller-owned,
+ * 16-byte aligned.  The chirp is read only.
+ * Errors: LBF_E_INVAL for sizes < 1, an unsupported n_fft, T not a multiple
+ * of n_fft, NULL, misaligned or partly overlapping buffers, or more than
+ * 2^31 - 1 blocks (C B T / n_fft).
+ */
+int lbf_dedisperse(const void* d_y, int C, int B, int T, int n_fft, const void* d_chirp, void* d_out,
+                   void* stream);
+
+/*
  * Peak probes, for reporting the kernels' rooflines against what this device
  * sustains beside the datasheet figures (not part of the beam former).
  *   kind 0: a register-only loop of MFMA 32x32x16 f16 (the FP16 contraction's

@@ -235,6 +235,27 @@ int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product,
     return ok();
 }
 
+int lbf_dedisperse(const void* d_y, int C, int B, int T, int n_fft, const void* d_chirp, void* d_out, void* stream) {
+    if (C < 1 || B < 1 || T < 1) return fail(LBF_E_INVAL, "lbf_dedisperse: sizes must be >= 1");
+    if (n_fft != 8 && n_fft != 64 && n_fft != 512 && n_fft != 4096)
+        return fail(LBF_E_INVAL, "lbf_dedisperse: n_fft must be 8, 64, 512 or 4096 (got %d)", n_fft);
+    if (T % n_fft) return fail(LBF_E_INVAL, "lbf_dedisperse: T=%d is not a multiple of n_fft=%d", T, n_fft);
+    if (!d_y || !d_chirp || !d_out) return fail(LBF_E_INVAL, "lbf_dedisperse: NULL device pointer");
+    if (((uintptr_t)d_y | (uintptr_t)d_chirp | (uintptr_t)d_out) & 15)
+        return fail(LBF_E_INVAL, "lbf_dedisperse: buffers must be 16-byte aligned");
+    if ((long long)C * B * (T / n_fft) > 0x7fffffffLL) return fail(LBF_E_INVAL, "lbf_dedisperse: too many blocks");
+    const size_t bytes = (size_t)C * B * T * 16;
+    const char* a = (const char*)d_y;
+    const char* o = (const char*)d_out;
+    if (a != o && a < o + bytes && o < a + bytes) return fail(LBF_E_INVAL, "lbf_dedisperse: input and output overlap");
+    const char* h = (const char*)d_chirp;
+    const size_t hbytes = (size_t)C * n_fft * 8;
+    if (h < o + bytes && o < h + hbytes) return fail(LBF_E_INVAL, "lbf_dedisperse: chirp and output overlap");
+    hipError_t e = lbf::launch_dedisperse(d_y, C, B, T, n_fft, d_chirp, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_dedisperse");
+    return ok();
+}
+
 int lbf_probe(int kind, int iters, const void* d_src, void* d_dst, uint64_t bytes, double* work, void* stream) {
     if (!work || !d_dst) return fail(LBF_E_INVAL, "lbf_probe: NULL pointer");
     if (kind < 0 || kind > 2) return fail(LBF_E_INVAL, "lbf_probe: unknown kind %d", kind);

@@ -1,0 +1,191 @@
+// dedisperse.hip -- channel-level dedispersion (Section 4.4 of Mol & Romein).
+// Each polarisation's beam voltages are cut into blocks of N = 8^P samples; a
+// block is Fourier transformed, multiplied bin by bin with the channel's
+// precomputed complex chirp weights, and transformed back with a 1/N factor.
+//
+// One work group per (channel, beam, block) keeps both polarisations of the
+// block in LDS (16 N bytes: 64 KiB at N = 4096) and runs radix-8 Stockham
+// passes.  Pass s (span Ns = 8^s) reads eight elements N/8 apart, turns them by
+// the twiddles exp(-2 pi i (j mod Ns) r / (8 Ns)), takes an 8-point DFT in
+// registers and writes the results Ns apart from (j / Ns) 8 Ns + j mod Ns;
+// after the last pass the spectrum is in natural order, with no bit reversal.
+// Every pass reads all its inputs, meets a barrier, then writes, so one
+// buffer serves in place.  The backward transform is the forward one applied
+// to conjugated data: the last forward pass multiplies by the chirp and
+// conjugates, the last backward pass conjugates and scales.  The first pass
+// reads HBM and the last writes HBM, each as 16-byte vectors (both
+// polarisations of one sample) of consecutive samples.  Bound: HBM.
+#include "lbf_device.h"
+#include "lbf_launch.h"
+
+namespace lbf {
+
+constexpr int kDdThreads = 256;
+typedef float cfl __attribute__((ext_vector_type(2)));   // (re, im)
+
+__device__ __forceinline__ cfl cmul(cfl a, cfl b) {
+    cfl r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+__device__ __forceinline__ cfl mk(float re, float im) {
+    cfl r;
+    r.x = re;
+    r.y = im;
+    return r;
+}
+
+// 4-point DFT, forward sign: X1 = (a0 - a2) - i (a1 - a3), X3 = (a0 - a2) + i (a1 - a3)
+__device__ __forceinline__ void dft4(cfl& a0, cfl& a1, cfl& a2, cfl& a3) {
+    const cfl s02 = a0 + a2, d02 = a0 - a2, s13 = a1 + a3, d13 = a1 - a3;
+    a0 = s02 + s13;
+    a2 = s02 - s13;
+    a1 = mk(d02.x + d13.y, d02.y - d13.x);
+    a3 = mk(d02.x - d13.y, d02.y + d13.x);
+}
+
+// 8-point DFT, forward sign, in place: 4-point DFTs of the even and the odd
+// elements, then X[k] = E[k] + W8^k O[k], X[k + 4] = E[k] - W8^k O[k]
+__device__ __forceinline__ void dft8(cfl* v) {
+    cfl e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cfl o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    const float h = 0.70710678118654752f;                  // sqrt(1/2)
+    const cfl t1 = mk(h * (o1.x + o1.y), h * (o1.y - o1.x));   // W8^1 o1
+    const cfl t2 = mk(o2.y, -o2.x);                            // W8^2 o2 = -i o2
+    const cfl t3 = mk(h * (o3.y - o3.x), -h * (o3.x + o3.y));  // W8^3 o3
+    v[0] = e0 + o0;
+    v[4] = e0 - o0;
+    v[1] = e1 + t1;
+    v[5] = e1 - t1;
+    v[2] = e2 + t2;
+    v[6] = e2 - t2;
+    v[3] = e3 + t3;
+    v[7] = e3 - t3;
+}
+
+// One Stockham pass over both polarisations.  SRC 0: the block in HBM,
+// 1: LDS.  DST 0: LDS, 1: LDS after the chirp product and conjugation (last
+// forward pass), 2: HBM after conjugation and 1/N (last backward pass).
+template <int N, int SRC, int DST>
+__device__ __forceinline__ void dd_pass(int Ns, cfl* buf, const floatx4* __restrict__ yb, const cfl* __restrict__ hc,
+                                        floatx4* __restrict__ ob) {
+    constexpr int Q = N / 8;                                // butterflies per polarisation
+    constexpr int JPT = (Q + kDdThreads - 1) / kDdThreads;  // per thread
+    cfl v[JPT][2][8];
+#pragma unroll
+    for (int m = 0; m < JPT; ++m) {
+        const int j = threadIdx.x + kDdThreads * m;
+        if (Q % kDdThreads != 0 && j >= Q) continue;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = j + r * Q;
+            if (SRC == 0) {
+                const floatx4 q = __builtin_nontemporal_load(yb + i);
+                v[m][0][r] = mk(q[0], q[1]);
+                v[m][1][r] = mk(q[2], q[3]);
+            } else {
+                v[m][0][r] = buf[i];
+                v[m][1][r] = buf[N + i];
+            }
+        }
+        if (Ns > 1) {
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 1; r < 8; ++r) {
+                float sn, cs;
+                sincospif(-(float)(k * r) / (float)(4 * Ns), &sn, &cs);   // exact argument: 4 Ns is a power of two
+                const cfl w = mk(cs, sn);
+                v[m][0][r] = cmul(v[m][0][r], w);
+                v[m][1][r] = cmul(v[m][1][r], w);
+            }
+        }
+        dft8(v[m][0]);
+        dft8(v[m][1]);
+    }
+    if (DST != 2) __syncthreads();                         // every read of this pass before any write
+#pragma unroll
+    for (int m = 0; m < JPT; ++m) {
+        const int j = threadIdx.x + kDdThreads * m;
+        if (Q % kDdThreads != 0 && j >= Q) continue;
+        const int d0 = (j / Ns) * Ns * 8 + j % Ns;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int n = d0 + r * Ns;
+            cfl a = v[m][0][r], b = v[m][1][r];
+            if (DST == 1) {
+                const cfl w = hc[n];
+                a = cmul(a, w);
+                b = cmul(b, w);
+                a.y = -a.y;
+                b.y = -b.y;
+            }
+            if (DST == 2) {
+                constexpr float inv = 1.0f / (float)N;      // a power of two: exact
+                floatx4 q;
+                q[0] = a.x * inv;
+                q[1] = -a.y * inv;
+                q[2] = b.x * inv;
+                q[3] = -b.y * inv;
+                __builtin_nontemporal_store(q, ob + n);
+            } else {
+                buf[n] = a;
+                buf[N + n] = b;
+            }
+        }
+    }
+    if (DST != 2) __syncthreads();                         // the writes before the next pass reads
+}
+
+template <int N>
+__global__ __launch_bounds__(kDdThreads) void dedisperse_kernel(const floatx4* __restrict__ y, const cfl* __restrict__ chirp,
+                                                                floatx4* __restrict__ out, int B, int T) {
+    __shared__ __attribute__((aligned(16))) cfl buf[2 * N];
+    const int nb = T / N;
+    const long wg = blockIdx.x;
+    const long cb = wg / nb;                                // c B + b
+    const int blk = (int)(wg - cb * nb);
+    const int c = (int)(cb / B);
+    const size_t base = (size_t)cb * T + (size_t)blk * N;   // in samples (16 bytes: both polarisations)
+    const floatx4* yb = y + base;
+    floatx4* ob = out + base;
+    const cfl* hc = chirp + (size_t)c * N;
+    constexpr int P = N == 8 ? 1 : N == 64 ? 2 : N == 512 ? 3 : 4;
+    // forward transform; its last pass applies the chirp and conjugates
+    int Ns = 1;
+    if (P == 1) {
+        dd_pass<N, 0, 1>(Ns, buf, yb, hc, ob);
+    } else {
+        dd_pass<N, 0, 0>(Ns, buf, yb, hc, ob);
+        Ns *= 8;
+        for (int s = 1; s < P - 1; ++s, Ns *= 8) dd_pass<N, 1, 0>(Ns, buf, yb, hc, ob);
+        dd_pass<N, 1, 1>(Ns, buf, yb, hc, ob);
+    }
+    // backward transform of the conjugated product; its last pass conjugates,
+    // scales and stores
+    Ns = 1;
+    for (int s = 0; s < P - 1; ++s, Ns *= 8) dd_pass<N, 1, 0>(Ns, buf, yb, hc, ob);
+    dd_pass<N, 1, 2>(Ns, buf, yb, hc, ob);
+}
+
+hipError_t launch_dedisperse(const void* y, int C, int B, int T, int n_fft, const void* chirp, void* out,
+                             hipStream_t st) {
+    const unsigned groups = (unsigned)((size_t)C * B * (T / n_fft));
+    const dim3 g(groups), b(kDdThreads);
+    const floatx4* yv = static_cast<const floatx4*>(y);
+    const cfl* hv = static_cast<const cfl*>(chirp);
+    floatx4* ov = static_cast<floatx4*>(out);
+    switch (n_fft) {
+        case 8: hipLaunchKernelGGL(dedisperse_kernel<8>, g, b, 0, st, yv, hv, ov, B, T); break;
+        case 64: hipLaunchKernelGGL(dedisperse_kernel<64>, g, b, 0, st, yv, hv, ov, B, T); break;
+        case 512: hipLaunchKernelGGL(dedisperse_kernel<512>, g, b, 0, st, yv, hv, ov, B, T); break;
+        case 4096: hipLaunchKernelGGL(dedisperse_kernel<4096>, g, b, 0, st, yv, hv, ov, B, T); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbf

@@ -93,6 +93,8 @@ _PROTOS = {
                                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_incoherent": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbf_dedisperse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_block_footprint": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.POINTER(BlockSizes)]),
     "lbf_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
@@ -310,6 +312,18 @@ def incoherent(x, product: int, t_int: int = 1, f_int: int = 1, out=None, stream
         out = torch.empty((n_stokes(product), T // t_int, C // f_int), dtype=torch.float32, device=x.device)
     _check(lib().lbf_incoherent(_dev_ptr(x, "x"), xtype_of(x), S, C, T, product, t_int, f_int,
                                 _dev_ptr(out, "out"), _stream(stream)))
+    return out
+
+
+def dedisperse(y, chirp, n_fft: int = 4096, out=None, stream=None):
+    """Channel-level dedispersion of voltages y [C][B][T][2][2] f32 with chirp
+    weights [C][n_fft][2] f32; returns [C][B][T][2][2] f32 (``out`` may be y)."""
+    torch = _torch()
+    C, B, T = y.shape[:3]
+    if out is None:
+        out = torch.empty_like(y)
+    _check(lib().lbf_dedisperse(_dev_ptr(y, "y"), C, B, T, n_fft, _dev_ptr(chirp, "chirp"), _dev_ptr(out, "out"),
+                                _stream(stream)))
     return out
 
 

@@ -69,6 +69,12 @@ def test_other_entry_points_validate_before_device_work():
     assert L.lbf_transpose(1, 2, 3, 4, 1, 16, 2, None) == lbf.E_INVAL          # elem_bytes
     assert L.lbf_transpose(4096, 2, 3, 4, 1, 4, 4100, None) == lbf.E_INVAL     # overlap
     assert L.lbf_incoherent(1, lbf.CI8, 4, 8, 10, lbf.STOKES_I, 4, 1, 1, None) == lbf.E_INVAL
+    assert L.lbf_dedisperse(16, 2, 3, 4096, 100, 16, 32, None) == lbf.E_INVAL           # n_fft
+    assert L.lbf_dedisperse(16, 2, 3, 1000, 512, 16, 32, None) == lbf.E_INVAL           # T % n_fft
+    assert L.lbf_dedisperse(None, 2, 3, 512, 512, 16, 32, None) == lbf.E_INVAL          # NULL
+    assert L.lbf_dedisperse(16, 2, 3, 512, 512, 16, 40, None) == lbf.E_INVAL            # alignment
+    assert L.lbf_dedisperse(4096, 2, 3, 512, 512, 16, 4096 + 16 * 512, None) == lbf.E_INVAL   # partial overlap
+    assert L.lbf_dedisperse(1 << 40, 2, 3, 512, 512, 1 << 20, 1 << 20, None) == lbf.E_INVAL  # chirp under the output
     arr = (lbf.Block * 2)(_block(ctype=lbf.F16), _block(ctype=lbf.F16))
     assert L.lbf_beamform_batch(arr, 0, None) == lbf.E_INVAL
     assert L.lbf_beamform_batch(arr, 33, None) == lbf.E_INVAL
