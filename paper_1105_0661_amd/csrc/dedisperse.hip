@@ -4,7 +4,7 @@
 // precomputed complex chirp weights, and transformed back with a 1/N factor.
 //
 // One work group per (channel, beam, block) keeps both polarisations of the
-// block in LDS (16 N bytes: 64 KiB at N = 4096) and runs radix-8 Stockham
+// block in LDS (16 N bytes plus padding: 66 KiB at N = 4096) and runs radix-8 Stockham
 // passes.  Pass s (span Ns = 8^s) reads eight elements N/8 apart, turns them by
 // the twiddles exp(-2 pi i (j mod Ns) r / (8 Ns)), takes an 8-point DFT in
 // registers and writes the results Ns apart from (j / Ns) 8 Ns + j mod Ns;
@@ -14,7 +14,8 @@
 // to conjugated data: the last forward pass multiplies by the chirp and
 // conjugates, the last backward pass conjugates and scales.  The first pass
 // reads HBM and the last writes HBM, each as 16-byte vectors (both
-// polarisations of one sample) of consecutive samples.  Bound: HBM.
+// polarisations of one sample) of consecutive samples.  Roofline: HBM (each
+// voltage is read and written once; the passes in between stay on chip).
 #include "lbf_device.h"
 #include "lbf_launch.h"
 
@@ -67,6 +68,13 @@ __device__ __forceinline__ void dft8(cfl* v) {
     v[7] = e3 - t3;
 }
 
+// LDS position of element n of a polarisation: one pad element after every
+// 32, which spreads the pass writes n = (j / Ns) 8 Ns + j mod Ns + r Ns of
+// neighbouring lanes over the banks
+__device__ __forceinline__ int lds_index(int n) { return n + (n >> 5); }
+template <int N>
+__host__ __device__ constexpr int lds_words() { return N + N / 32; }
+
 // One Stockham pass over both polarisations.  SRC 0: the block in HBM,
 // 1: LDS.  DST 0: LDS, 1: LDS after the chirp product and conjugation (last
 // forward pass), 2: HBM after conjugation and 1/N (last backward pass).
@@ -76,6 +84,7 @@ __device__ __forceinline__ void dd_pass(int Ns, cfl* buf, const floatx4* __restr
     constexpr int Q = N / 8;                                // butterflies per polarisation
     constexpr int JPT = (Q + kDdThreads - 1) / kDdThreads;  // per thread
     cfl v[JPT][2][8];
+    cfl w[8];                                               // twiddles of the thread's butterfly j
 #pragma unroll
     for (int m = 0; m < JPT; ++m) {
         const int j = threadIdx.x + kDdThreads * m;
@@ -88,19 +97,29 @@ __device__ __forceinline__ void dd_pass(int Ns, cfl* buf, const floatx4* __restr
                 v[m][0][r] = mk(q[0], q[1]);
                 v[m][1][r] = mk(q[2], q[3]);
             } else {
-                v[m][0][r] = buf[i];
-                v[m][1][r] = buf[N + i];
+                v[m][0][r] = buf[lds_index(i)];
+                v[m][1][r] = buf[lds_words<N>() + lds_index(i)];
             }
         }
         if (Ns > 1) {
-            const int k = j % Ns;
+            // w[r] = exp(-2 pi i k r / (8 Ns)), k = j mod Ns: w[1] from sincospif
+            // (exact argument: 4 Ns is a power of two), the others as products;
+            // the thread's later butterflies j + 256 m share k while Ns divides 256
+            if (m == 0 || kDdThreads % Ns != 0) {
+                float sn, cs;
+                sincospif(-(float)(j % Ns) / (float)(4 * Ns), &sn, &cs);
+                w[1] = mk(cs, sn);
+                w[2] = cmul(w[1], w[1]);
+                w[4] = cmul(w[2], w[2]);
+                w[3] = cmul(w[1], w[2]);
+                w[5] = cmul(w[1], w[4]);
+                w[6] = cmul(w[2], w[4]);
+                w[7] = cmul(w[3], w[4]);
+            }
 #pragma unroll
             for (int r = 1; r < 8; ++r) {
-                float sn, cs;
-                sincospif(-(float)(k * r) / (float)(4 * Ns), &sn, &cs);   // exact argument: 4 Ns is a power of two
-                const cfl w = mk(cs, sn);
-                v[m][0][r] = cmul(v[m][0][r], w);
-                v[m][1][r] = cmul(v[m][1][r], w);
+                v[m][0][r] = cmul(v[m][0][r], w[r]);
+                v[m][1][r] = cmul(v[m][1][r], w[r]);
             }
         }
         dft8(v[m][0]);
@@ -132,8 +151,8 @@ __device__ __forceinline__ void dd_pass(int Ns, cfl* buf, const floatx4* __restr
                 q[3] = -b.y * inv;
                 __builtin_nontemporal_store(q, ob + n);
             } else {
-                buf[n] = a;
-                buf[N + n] = b;
+                buf[lds_index(n)] = a;
+                buf[lds_words<N>() + lds_index(n)] = b;
             }
         }
     }
@@ -143,7 +162,7 @@ __device__ __forceinline__ void dd_pass(int Ns, cfl* buf, const floatx4* __restr
 template <int N>
 __global__ __launch_bounds__(kDdThreads) void dedisperse_kernel(const floatx4* __restrict__ y, const cfl* __restrict__ chirp,
                                                                 floatx4* __restrict__ out, int B, int T) {
-    __shared__ __attribute__((aligned(16))) cfl buf[2 * N];
+    __shared__ __attribute__((aligned(16))) cfl buf[2 * lds_words<N>()];
     const int nb = T / N;
     const long wg = blockIdx.x;
     const long cb = wg / nb;                                // c B + b
