@@ -3,8 +3,9 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this module.  The GPU library never calls it and shares
 no code with it.  The arithmetic lives in ``lbf_oracle.c`` (plain C, FP64);
-this file compiles it with gcc and marshals numpy arrays.  Dedispersion alone
-is written here in numpy (complex128), with numpy's FFT as its FFT step.
+this file compiles it with gcc and marshals numpy arrays.  The channeliser and
+dedispersion are written here in numpy (complex128), with numpy's FFT as their
+FFT step.
 
 Definitions followed (Mol & Romein, "The LOFAR Beam Former"):
 
@@ -18,6 +19,8 @@ Definitions followed (Mol & Romein, "The LOFAR Beam Former"):
 * ``integrate``  -- sums over t_int samples and f_int channels (Sec. 3, Sec. 5.1)
 * ``reorder``    -- final per-beam, per-Stokes order [b][k][t'][c'] (Sec. 4.6)
 * ``incoherent`` -- sum over stations of per-station Stokes (Sec. 3)
+* ``channelize`` -- the FFT that splits each subband into channels (Sec. 4.2):
+  nch consecutive subband samples -> nch channels, lowest frequency first
 * ``dedisperse`` -- channel-level dedispersion (Sec. 4.4): per block of
   n_fft samples a forward FFT, a product with the channel's precomputed
   complex chirp weights, and a backward FFT; numpy's FFT is the FFT step
@@ -216,3 +219,22 @@ def dedisperse(y: np.ndarray, chirp: np.ndarray, n_fft: int) -> np.ndarray:
     spec = spec * chirp[:, None, None, :, None]              # the channel's chirp, same for every beam
     out = np.fft.ifft(spec, axis=3)                          # backward, with the 1/n_fft factor
     return out.reshape(C, B, T, P)
+
+
+def channelize(x: np.ndarray, nch: int) -> np.ndarray:
+    """Channeliser (Sec. 4.2): each subband's complex time series (per station
+    and polarisation) is cut into consecutive groups of nch samples; the FFT
+    of a group (forward sign, no window, no scaling) gives its nch channels.
+    Channel q of subband sb is FFT bin (q + nch/2) mod nch, so channels run
+    from the lowest frequency (q = 0, nch/2 channel widths below the subband's
+    centre) upwards.  x: [S][NSB][T_sb][2][2] (re, im last; int8, int16 or
+    float32).  Returns complex128 [S][NSB nch][T_sb / nch][2]."""
+    x = np.asarray(x)
+    S, NSB, Tsb = x.shape[:3]
+    if Tsb % nch:
+        raise ValueError("T_sb must be a multiple of nch")
+    xc = x[..., 0].astype(np.float64) + 1j * x[..., 1].astype(np.float64)      # [S][NSB][T_sb][2]
+    groups = xc.reshape(S, NSB, Tsb // nch, nch, 2)
+    spec = np.fft.fft(groups, axis=3)                                           # bin k
+    spec = np.fft.fftshift(spec, axes=3)                                        # channel q = bin (q + nch/2) mod nch
+    return spec.transpose(0, 1, 3, 2, 4).reshape(S, NSB * nch, Tsb // nch, 2)

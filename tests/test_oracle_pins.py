@@ -352,3 +352,51 @@ def test_dedisperse_unit_modulus_weights_keep_the_energy():
     chirp = np.exp(2j * np.pi * rng.random((2, n)))
     out = orc.dedisperse(y, chirp, n)
     assert abs(np.sum(np.abs(out) ** 2) / np.sum(np.abs(y) ** 2) - 1) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# channeliser (Sec. 4.2)
+# --------------------------------------------------------------------------
+
+def test_channelize_brute_force_dft_and_channel_order():
+    """Written out: channel q of subband sb at output time t is
+    sum_j x[t nch + j] exp(-2 pi i j k / nch) with k = (q + nch/2) mod nch."""
+    rng = np.random.default_rng([1105, 661, 95])
+    S, NSB, nch, T = 2, 2, 8, 16
+    x = rng.integers(-100, 101, size=(S, NSB, T, 2, 2)).astype(np.int16)
+    got = orc.channelize(x, nch)
+    assert got.shape == (S, NSB * nch, T // nch, 2)
+    for s in range(S):
+        for sb in range(NSB):
+            for t in range(T // nch):
+                for p in range(2):
+                    z = [complex(int(x[s, sb, t * nch + j, p, 0]), int(x[s, sb, t * nch + j, p, 1])) for j in range(nch)]
+                    for q in range(nch):
+                        k = (q + nch // 2) % nch
+                        want = sum(z[j] * cmath.exp(-2j * cmath.pi * j * k / nch) for j in range(nch))
+                        assert abs(got[s, sb * nch + q, t, p] - want) < 1e-9
+
+
+def test_channelize_tone_lands_in_its_channel():
+    """A complex tone at (q0 - nch/2) channel widths from the subband centre,
+    exp(2 pi i (q0 - nch/2) n / nch), puts all its power, nch per sample
+    squared, into channel q0 and nothing elsewhere."""
+    nch, T = 16, 64
+    n = np.arange(T)
+    for q0 in (0, 3, 8, 15):
+        tone = np.exp(2j * np.pi * (q0 - nch / 2) * n / nch)
+        x = np.zeros((1, 1, T, 2, 2), np.float32)
+        x[0, 0, :, 0, 0], x[0, 0, :, 0, 1] = tone.real, tone.imag
+        got = orc.channelize(x, nch)[0, :, :, 0]                 # [nch][T / nch]
+        assert np.allclose(np.abs(got[q0]), nch, atol=1e-4)
+        others = np.delete(got, q0, axis=0)
+        assert np.abs(others).max() < 1e-4
+
+
+def test_channelize_energy_and_one_channel_identity():
+    rng = np.random.default_rng([1105, 661, 96])
+    x = rng.integers(-128, 128, size=(2, 3, 256, 2, 2)).astype(np.int8)
+    got = orc.channelize(x, 64)
+    xc = x[..., 0].astype(np.float64) + 1j * x[..., 1]
+    assert abs(np.sum(np.abs(got) ** 2) / (64 * np.sum(np.abs(xc) ** 2)) - 1) < 1e-12     # Parseval
+    assert np.array_equal(orc.channelize(x, 1), xc)                                      # nch = 1: no change
