@@ -164,6 +164,38 @@ def incoherent(lbf, torch, x, steps, warmup, mp):
     return r
 
 
+def channelizer(lbf, torch, dev, steps, warmup, mp):
+    """The channeliser ahead of the one-second block: 64 stations x 32
+    subbands of 196608 complex int16 samples (1.0066 s at 195 kHz), 256
+    channels per subband -> the block's [64][8192][768][2] channels in
+    complex f32.  Seeded uniform int16 samples generated on the device.
+    HBM-bound: every sample read once, every channel sample written once."""
+    S, NSB, nch = 64, 32, 256
+    T_sb = 768 * nch
+    gen = torch.Generator(device=dev).manual_seed(1105661)
+    x = torch.randint(-300, 301, (S, NSB, T_sb, 2, 2), generator=gen, device=dev, dtype=torch.int16)
+    out = torch.empty((S, NSB * nch, T_sb // nch, 2, 2), dtype=torch.float32, device=dev)
+    nrep = warmup + steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(nrep)]
+    for i in range(nrep):
+        ev[i][0].record()
+        lbf.channelize(x, nch, out=out)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(warmup, nrep)]))
+    nbytes = S * NSB * T_sb * 8 + S * NSB * T_sb * 16
+    gbps = nbytes / (ms / 1e3) / 1e9
+    r = {"workload": "channeliser of the one-second block: 64 stations, 32 subbands x 196608 complex int16 "
+                     "samples, 2 pols -> 256 channels per subband, complex f32",
+         "kernel_ms": ms, "algorithmic_bytes": nbytes, "hbm_GBps": gbps, "bound": "hbm",
+         "frac": gbps / PEAK["hbm_GBps"],
+         "input_Gbps": S * NSB * T_sb * 64 / (ms / 1e3) / 1e9}
+    if mp:
+        r["frac_of_measured_copy"] = gbps / mp["hbm_GBps"]
+    del x, out
+    return r
+
+
 def dedispersion(lbf, torch, dev, steps, warmup, mp):
     """Channel-level dedispersion at Table 1 case E's shape on one GPU's share
     of the subbands: 32 subbands x 16 channels (12.2 kHz), 10 beams, three
@@ -505,7 +537,7 @@ def main():
 
     # ---------------- the 488-beam precision block (MFMA-bound) ----------------
     extra = None
-    batch_res = serve_res = unfused_res = inc_res = dd_res = None
+    batch_res = serve_res = unfused_res = inc_res = dd_res = ch_res = None
     if not a.no_extra and not only:
         unfused_res = unfused(lbf, torch, x, geo, 1024, max(3, a.steps // 4), 1)
         log("unfused chain: %s" % unfused_res)
@@ -513,6 +545,8 @@ def main():
         log("incoherent beam: %s" % inc_res)
         dd_res = dedispersion(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp)
         log("dedispersion: %s" % dd_res)
+        ch_res = channelizer(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp)
+        log("channeliser: %s" % ch_res)
         b2 = synth.config2(threads=16)
         x2 = torch.from_numpy(b2.x).to(dev)
         geo2 = (torch.from_numpy(b2.station_xyz).to(dev), torch.from_numpy(b2.beam_dir).to(dev),
@@ -615,6 +649,8 @@ def main():
         line["incoherent_beam"] = inc_res
     if dd_res:
         line["dedispersion"] = dd_res
+    if ch_res:
+        line["channeliser"] = ch_res
     if batch_res:
         line["batched"] = batch_res
     if serve_res:

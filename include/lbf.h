@@ -184,6 +184,22 @@ int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product,
                    int f_int, float* d_out, void* stream);
 
 /*
+ * Channeliser (Section 4.2: an FFT divides each subband into channels): every
+ * station's and polarisation's subband series is cut into consecutive groups
+ * of nch samples; the FFT of a group (forward sign exp(-2 pi i j k / nch), no
+ * window, no scaling) gives one sample of each of the subband's nch channels,
+ * lowest frequency first: channel q is FFT bin (q + nch/2) mod nch.
+ *   d_x   [S][NSB][T_sb][2] complex of xtype (re, im interleaved), 16-byte aligned
+ *   d_out complex f32 [S][NSB nch][T_sb / nch][2], the layout lbf_beamform takes
+ *         as CF32 input (C = NSB nch, T = T_sb / nch); must not overlap d_x
+ * nch is a power of two from 2 to 256; T_sb must be a multiple of nch.
+ * Errors: LBF_E_INVAL for sizes < 1, an unsupported nch, T_sb not a multiple
+ * of nch, an unknown xtype, NULL, misaligned or overlapping buffers, or a grid
+ * of more than 2^31 - 1 work groups.
+ */
+int lbf_channelize(const void* d_x, int xtype, int S, int NSB, int T_sb, int nch, float* d_out, void* stream);
+
+/*
  * Channel-level dedispersion (Section 4.4): each polarisation's beam voltages
  * are cut into blocks of n_fft consecutive samples; each block is Fourier
  * transformed (forward sign exp(-2 pi i j k / n_fft)), multiplied bin by bin

@@ -1,0 +1,138 @@
+// channelize.hip -- the FFT that splits each subband into channels (Section
+// 4.2 of Mol & Romein): every station's and polarisation's subband time
+// series is cut into consecutive groups of nch samples, and the FFT of a
+// group (forward sign, no window, no scaling) gives one sample of each of the
+// subband's nch channels, lowest frequency first (channel q = FFT bin
+// (q + nch/2) mod nch).
+//
+// One work group per tile of kChTile consecutive samples of one (station,
+// subband) row, both polarisations, in LDS (33 KiB with padding):
+//   1. coalesced loads of the tile's samples, converted to float;
+//   2. Stockham passes over the tile's kChTile / nch spectra: one radix-2
+//      pass when log2 nch is odd, then radix-4 passes; each pass reads all
+//      its inputs, meets a barrier, and writes in place; the spectra come
+//      out in natural order;
+//   3. stores in channel order, consecutive lanes on consecutive output
+//      times of one channel: out[s][sb nch + q][t][p], 16 bytes (both
+//      polarisations) per lane.
+// Roofline: HBM (every sample read once, every channel sample written once).
+#include "fft_device.h"
+#include "lbf_launch.h"
+
+namespace lbf {
+
+constexpr int kChThreads = 256;
+constexpr int kChTile = 2048;                         // samples per polarisation in a tile
+constexpr int kChWords = kChTile + kChTile / 32;      // LDS words per polarisation, padded
+
+// One radix-R (2 or 4) pass of span Ns over every spectrum of the tile.
+template <int R>
+__device__ __forceinline__ void ch_pass(cfl* buf, int nch, int Ns) {
+    constexpr int G = kChTile / R;                    // butterflies per polarisation
+    constexpr int BPT = G / kChThreads;               // per thread
+    const int nb = nch / R;                           // butterflies per spectrum
+    cfl v[BPT][2][R];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int g = threadIdx.x + kChThreads * u;
+        const int m = g / nb, j = g - m * nb;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int n = m * nch + j + r * nb;
+            v[u][0][r] = buf[lds_index(n)];
+            v[u][1][r] = buf[kChWords + lds_index(n)];
+        }
+        if (Ns > 1) {
+            // exp(-2 pi i k r / (R Ns)), k = j mod Ns; exact argument (R Ns is a power of two)
+            float sn, cs;
+            sincospif(-2.0f * (float)(j % Ns) / (float)(R * Ns), &sn, &cs);
+            cfl w[R];
+            w[1] = mk(cs, sn);
+            if (R == 4) {
+                w[2] = cmul(w[1], w[1]);
+                w[3] = cmul(w[1], w[2]);
+            }
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                v[u][0][r] = cmul(v[u][0][r], w[r]);
+                v[u][1][r] = cmul(v[u][1][r], w[r]);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            if (R == 2) {
+                const cfl a = v[u][p][0], b = v[u][p][1];
+                v[u][p][0] = a + b;
+                v[u][p][1] = a - b;
+            } else {
+                dft4(v[u][p][0], v[u][p][1], v[u][p][2], v[u][p][3]);
+            }
+        }
+    }
+    __syncthreads();                                  // every read of this pass before any write
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int g = threadIdx.x + kChThreads * u;
+        const int m = g / nb, j = g - m * nb;
+        const int d0 = m * nch + (j / Ns) * Ns * R + j % Ns;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            buf[lds_index(d0 + r * Ns)] = v[u][0][r];
+            buf[kChWords + lds_index(d0 + r * Ns)] = v[u][1][r];
+        }
+    }
+    __syncthreads();                                  // the writes before the next pass reads
+}
+
+template <int XT>
+__global__ __launch_bounds__(kChThreads) void channelize_kernel(const void* __restrict__ x, int NSB, int Tsb, int nch,
+                                                                int ntile, floatx4* __restrict__ out) {
+    __shared__ __attribute__((aligned(16))) cfl buf[2 * kChWords];
+    const int M = kChTile / nch;                      // spectra per tile
+    const int T2 = Tsb / nch;
+    const long wg = blockIdx.x;
+    const long row = wg / ntile;                      // s NSB + sb
+    const int t0 = (int)(wg - row * ntile) * M;
+    const int nvalid = min(M, T2 - t0) * nch;         // samples of the tile inside the row
+    const size_t in0 = (size_t)row * Tsb + (size_t)t0 * nch;
+    for (int i = threadIdx.x; i < kChTile; i += kChThreads) {
+        floatx4 v = {0.f, 0.f, 0.f, 0.f};
+        if (i < nvalid) v = Sample<XT>::load(x, in0 + i);
+        buf[lds_index(i)] = mk(v[0], v[1]);
+        buf[kChWords + lds_index(i)] = mk(v[2], v[3]);
+    }
+    __syncthreads();
+    int Ns = 1;
+    if (__builtin_ctz(nch) & 1) {
+        ch_pass<2>(buf, nch, Ns);
+        Ns = 2;
+    }
+    for (; Ns < nch; Ns *= 4) ch_pass<4>(buf, nch, Ns);
+    const int s = (int)(row / NSB), sb = (int)(row - (long)s * NSB);
+    const size_t C = (size_t)NSB * nch;
+    for (int e = threadIdx.x; e < kChTile; e += kChThreads) {
+        const int q = e / M, m = e - q * M;
+        if (t0 + m >= T2) continue;
+        const int n = m * nch + ((q + nch / 2) & (nch - 1));
+        const cfl a = buf[lds_index(n)], b = buf[kChWords + lds_index(n)];
+        floatx4 o;
+        o[0] = a.x;
+        o[1] = a.y;
+        o[2] = b.x;
+        o[3] = b.y;
+        __builtin_nontemporal_store(o, out + ((size_t)s * C + (size_t)sb * nch + q) * T2 + t0 + m);
+    }
+}
+
+hipError_t launch_channelize(const void* x, int xtype, int S, int NSB, int Tsb, int nch, float* out, hipStream_t st) {
+    const int M = kChTile / nch;
+    const int ntile = (Tsb / nch + M - 1) / M;
+    const dim3 g((unsigned)((size_t)S * NSB * ntile)), b(kChThreads);
+    floatx4* o = reinterpret_cast<floatx4*>(out);
+    if (xtype == XT_CI8) hipLaunchKernelGGL(channelize_kernel<XT_CI8>, g, b, 0, st, x, NSB, Tsb, nch, ntile, o);
+    else if (xtype == XT_CI16) hipLaunchKernelGGL(channelize_kernel<XT_CI16>, g, b, 0, st, x, NSB, Tsb, nch, ntile, o);
+    else hipLaunchKernelGGL(channelize_kernel<XT_CF32>, g, b, 0, st, x, NSB, Tsb, nch, ntile, o);
+    return hipGetLastError();
+}
+
+}  // namespace lbf

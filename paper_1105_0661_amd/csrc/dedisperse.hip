@@ -16,36 +16,12 @@
 // reads HBM and the last writes HBM, each as 16-byte vectors (both
 // polarisations of one sample) of consecutive samples.  Roofline: HBM (each
 // voltage is read and written once; the passes in between stay on chip).
-#include "lbf_device.h"
+#include "fft_device.h"
 #include "lbf_launch.h"
 
 namespace lbf {
 
 constexpr int kDdThreads = 256;
-typedef float cfl __attribute__((ext_vector_type(2)));   // (re, im)
-
-__device__ __forceinline__ cfl cmul(cfl a, cfl b) {
-    cfl r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-
-__device__ __forceinline__ cfl mk(float re, float im) {
-    cfl r;
-    r.x = re;
-    r.y = im;
-    return r;
-}
-
-// 4-point DFT, forward sign: X1 = (a0 - a2) - i (a1 - a3), X3 = (a0 - a2) + i (a1 - a3)
-__device__ __forceinline__ void dft4(cfl& a0, cfl& a1, cfl& a2, cfl& a3) {
-    const cfl s02 = a0 + a2, d02 = a0 - a2, s13 = a1 + a3, d13 = a1 - a3;
-    a0 = s02 + s13;
-    a2 = s02 - s13;
-    a1 = mk(d02.x + d13.y, d02.y - d13.x);
-    a3 = mk(d02.x - d13.y, d02.y + d13.x);
-}
 
 // 8-point DFT, forward sign, in place: 4-point DFTs of the even and the odd
 // elements, then X[k] = E[k] + W8^k O[k], X[k + 4] = E[k] - W8^k O[k]
@@ -68,10 +44,7 @@ __device__ __forceinline__ void dft8(cfl* v) {
     v[7] = e3 - t3;
 }
 
-// LDS position of element n of a polarisation: one pad element after every
-// 32, which spreads the pass writes n = (j / Ns) 8 Ns + j mod Ns + r Ns of
-// neighbouring lanes over the banks
-__device__ __forceinline__ int lds_index(int n) { return n + (n >> 5); }
+// LDS words of one polarisation's block, with lds_index's padding
 template <int N>
 __host__ __device__ constexpr int lds_words() { return N + N / 32; }
 

@@ -93,6 +93,8 @@ _PROTOS = {
                                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_incoherent": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbf_channelize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_dedisperse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_block_footprint": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.POINTER(BlockSizes)]),
@@ -312,6 +314,18 @@ def incoherent(x, product: int, t_int: int = 1, f_int: int = 1, out=None, stream
         out = torch.empty((n_stokes(product), T // t_int, C // f_int), dtype=torch.float32, device=x.device)
     _check(lib().lbf_incoherent(_dev_ptr(x, "x"), xtype_of(x), S, C, T, product, t_int, f_int,
                                 _dev_ptr(out, "out"), _stream(stream)))
+    return out
+
+
+def channelize(x, nch: int, out=None, stream=None):
+    """Subband samples x [S][NSB][T_sb][2][2] (int8/int16/float32) -> channels
+    [S][NSB nch][T_sb / nch][2][2] f32, lowest frequency first."""
+    torch = _torch()
+    S, NSB, Tsb = x.shape[:3]
+    if out is None:
+        out = torch.empty((S, NSB * nch, Tsb // nch, 2, 2), dtype=torch.float32, device=x.device)
+    _check(lib().lbf_channelize(_dev_ptr(x, "x"), xtype_of(x), S, NSB, Tsb, nch, _dev_ptr(out, "out"),
+                                _stream(stream)))
     return out
 
 
