@@ -221,19 +221,31 @@ def dedisperse(y: np.ndarray, chirp: np.ndarray, n_fft: int) -> np.ndarray:
     return out.reshape(C, B, T, P)
 
 
-def channelize(x: np.ndarray, nch: int) -> np.ndarray:
-    """Channeliser (Sec. 4.2): each subband's complex time series (per station
-    and polarisation) is cut into consecutive groups of nch samples; the FFT
-    of a group (forward sign, no window, no scaling) gives its nch channels.
-    Channel q of subband sb is FFT bin (q + nch/2) mod nch, so channels run
-    from the lowest frequency (q = 0, nch/2 channel widths below the subband's
-    centre) upwards.  x: [S][NSB][T_sb][2][2] (re, im last; int8, int16 or
-    float32).  Returns complex128 [S][NSB nch][T_sb / nch][2]."""
+def channelize(x: np.ndarray, nch: int, t_sb: int | None = None, shift=None) -> np.ndarray:
+    """Channeliser (Sec. 4.2) with sample-granularity delay compensation
+    (Sec. 3: station series are shifted against each other by whole samples).
+    Station s contributes its subband samples [shift[s], shift[s] + t_sb) of
+    x (samples outside the row count as zero); each subband's complex time
+    series (per station and polarisation) is then cut into consecutive groups
+    of nch samples, and the FFT of a group (forward sign, no window, no
+    scaling) gives its nch channels.  Channel q of subband sb is FFT bin
+    (q + nch/2) mod nch, so channels run from the lowest frequency (q = 0,
+    nch/2 channel widths below the subband's centre) upwards.
+    x: [S][NSB][T_in][2][2] (re, im last; int8, int16 or float32); t_sb
+    defaults to T_in and shift to zeros.  Returns complex128
+    [S][NSB nch][t_sb / nch][2]."""
     x = np.asarray(x)
-    S, NSB, Tsb = x.shape[:3]
+    S, NSB, Tin = x.shape[:3]
+    Tsb = Tin if t_sb is None else t_sb
     if Tsb % nch:
         raise ValueError("T_sb must be a multiple of nch")
-    xc = x[..., 0].astype(np.float64) + 1j * x[..., 1].astype(np.float64)      # [S][NSB][T_sb][2]
+    xin = x[..., 0].astype(np.float64) + 1j * x[..., 1].astype(np.float64)     # [S][NSB][T_in][2]
+    xc = np.zeros((S, NSB, Tsb, 2), np.complex128)
+    for st in range(S):                                                         # the shifted window
+        d = 0 if shift is None else int(shift[st])
+        lo, hi = max(d, 0), min(d + Tsb, Tin)
+        if hi > lo:
+            xc[st, :, lo - d:hi - d] = xin[st, :, lo:hi]
     groups = xc.reshape(S, NSB, Tsb // nch, nch, 2)
     spec = np.fft.fft(groups, axis=3)                                           # bin k
     spec = np.fft.fftshift(spec, axes=3)                                        # channel q = bin (q + nch/2) mod nch

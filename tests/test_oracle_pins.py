@@ -400,3 +400,28 @@ def test_channelize_energy_and_one_channel_identity():
     xc = x[..., 0].astype(np.float64) + 1j * x[..., 1]
     assert abs(np.sum(np.abs(got) ** 2) / (64 * np.sum(np.abs(xc) ** 2)) - 1) < 1e-12     # Parseval
     assert np.array_equal(orc.channelize(x, 1), xc)                                      # nch = 1: no change
+
+
+def test_channelize_shift_makes_delayed_stations_coherent():
+    """Station 1 receives station 0's signal d samples later; shifting it by d
+    (sample-level delay compensation) makes its channels equal to station 0's,
+    while without the shift they differ."""
+    rng = np.random.default_rng([1105, 661, 99])
+    nch, T, d = 16, 256, 5
+    sig = rng.integers(-500, 501, size=(1, 2, T + 32, 2, 2)).astype(np.int16)
+    x = np.zeros((2, 2, T + 32, 2, 2), np.int16)
+    x[0] = sig[0]
+    x[1, :, d:] = sig[0, :, :T + 32 - d]                       # the same wave, d samples later
+    got = orc.channelize(x, nch, t_sb=T, shift=[0, d])
+    assert np.allclose(got[1], got[0], rtol=0, atol=1e-9)
+    plain = orc.channelize(x, nch, t_sb=T)
+    assert np.abs(plain[1] - plain[0]).max() > 1.0
+
+
+def test_channelize_shift_reads_zero_outside_the_row():
+    x = np.ones((1, 1, 32, 2, 2), np.float32)
+    got = orc.channelize(x, 8, t_sb=32, shift=[24])            # 8 samples inside, 24 past the end
+    assert np.allclose(got[0, :, 0, 0], 8 * (1 + 1j) * (np.arange(8) == 4), atol=1e-12)   # DC: channel nch/2
+    assert np.abs(got[0, :, 1:]).max() == 0
+    neg = orc.channelize(x, 8, t_sb=16, shift=[-8])            # the first group lies before the row
+    assert np.abs(neg[0, :, 0]).max() == 0 and abs(neg[0, 4, 1, 0] - 8 * (1 + 1j)) < 1e-12
