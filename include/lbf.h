@@ -184,20 +184,28 @@ int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product,
                    int f_int, float* d_out, void* stream);
 
 /*
- * Channeliser (Section 4.2: an FFT divides each subband into channels): every
- * station's and polarisation's subband series is cut into consecutive groups
- * of nch samples; the FFT of a group (forward sign exp(-2 pi i j k / nch), no
- * window, no scaling) gives one sample of each of the subband's nch channels,
- * lowest frequency first: channel q is FFT bin (q + nch/2) mod nch.
- *   d_x   [S][NSB][T_sb][2] complex of xtype (re, im interleaved), 16-byte aligned
- *   d_out complex f32 [S][NSB nch][T_sb / nch][2], the layout lbf_beamform takes
- *         as CF32 input (C = NSB nch, T = T_sb / nch); must not overlap d_x
+ * Channeliser (Section 4.2: an FFT divides each subband into channels), with
+ * the sample-granularity part of delay compensation (Section 3: station
+ * series are shifted against each other by whole samples; the sub-sample part
+ * is in the beam former's weights).  Station s contributes the window of T_sb
+ * samples that starts d_shift[s] samples into its row (samples outside
+ * [0, T_in) read as zero; NULL d_shift: no shift).  Every station's and
+ * polarisation's window is cut into consecutive groups of nch samples; the
+ * FFT of a group (forward sign exp(-2 pi i j k / nch), no window function, no
+ * scaling) gives one sample of each of the subband's nch channels, lowest
+ * frequency first: channel q is FFT bin (q + nch/2) mod nch.
+ *   d_x     [S][NSB][T_in][2] complex of xtype (re, im interleaved), 16-byte aligned
+ *   d_shift device int32 [S] (any values) or NULL
+ *   d_out   complex f32 [S][NSB nch][T_sb / nch][2], the layout lbf_beamform
+ *           takes as CF32 input (C = NSB nch, T = T_sb / nch); must not
+ *           overlap d_x or d_shift
  * nch is a power of two from 2 to 256; T_sb must be a multiple of nch.
  * Errors: LBF_E_INVAL for sizes < 1, an unsupported nch, T_sb not a multiple
  * of nch, an unknown xtype, NULL, misaligned or overlapping buffers, or a grid
  * of more than 2^31 - 1 work groups.
  */
-int lbf_channelize(const void* d_x, int xtype, int S, int NSB, int T_sb, int nch, float* d_out, void* stream);
+int lbf_channelize(const void* d_x, int xtype, int S, int NSB, int T_in, int T_sb, int nch, const int* d_shift,
+                   float* d_out, void* stream);
 
 /*
  * Channel-level dedispersion (Section 4.4): each polarisation's beam voltages

@@ -235,22 +235,27 @@ int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product,
     return ok();
 }
 
-int lbf_channelize(const void* d_x, int xtype, int S, int NSB, int T_sb, int nch, float* d_out, void* stream) {
-    if (S < 1 || NSB < 1 || T_sb < 1) return fail(LBF_E_INVAL, "lbf_channelize: sizes must be >= 1");
+int lbf_channelize(const void* d_x, int xtype, int S, int NSB, int T_in, int T_sb, int nch, const int* d_shift,
+                   float* d_out, void* stream) {
+    if (S < 1 || NSB < 1 || T_in < 1 || T_sb < 1) return fail(LBF_E_INVAL, "lbf_channelize: sizes must be >= 1");
     if (nch < 2 || nch > 256 || (nch & (nch - 1)))
         return fail(LBF_E_INVAL, "lbf_channelize: nch must be a power of two from 2 to 256 (got %d)", nch);
     if (T_sb % nch) return fail(LBF_E_INVAL, "lbf_channelize: T_sb=%d is not a multiple of nch=%d", T_sb, nch);
     if (xtype < LBF_CI8 || xtype > LBF_CF32) return fail(LBF_E_INVAL, "lbf_channelize: unknown xtype %d", xtype);
     if (!d_x || !d_out) return fail(LBF_E_INVAL, "lbf_channelize: NULL device pointer");
     if (((uintptr_t)d_x | (uintptr_t)d_out) & 15) return fail(LBF_E_INVAL, "lbf_channelize: buffers must be 16-byte aligned");
+    if (((uintptr_t)d_shift) & 3) return fail(LBF_E_INVAL, "lbf_channelize: shift must be 4-byte aligned");
     const long long tiles = (T_sb / nch + 2048 / nch - 1) / (2048 / nch);
     if ((long long)S * NSB * tiles > 0x7fffffffLL) return fail(LBF_E_INVAL, "lbf_channelize: too large");
-    const size_t in_bytes = (size_t)S * NSB * T_sb * (xtype == LBF_CI8 ? 4 : xtype == LBF_CI16 ? 8 : 16);
+    const size_t in_bytes = (size_t)S * NSB * T_in * (xtype == LBF_CI8 ? 4 : xtype == LBF_CI16 ? 8 : 16);
     const size_t out_bytes = (size_t)S * NSB * T_sb * 16;
     const char* a = (const char*)d_x;
     const char* o = (const char*)d_out;
     if (a < o + out_bytes && o < a + in_bytes) return fail(LBF_E_INVAL, "lbf_channelize: input and output overlap");
-    hipError_t e = lbf::launch_channelize(d_x, xtype, S, NSB, T_sb, nch, d_out, (hipStream_t)stream);
+    const char* sh = (const char*)d_shift;
+    if (sh && sh < o + out_bytes && o < sh + (size_t)S * sizeof(int))
+        return fail(LBF_E_INVAL, "lbf_channelize: shift and output overlap");
+    hipError_t e = lbf::launch_channelize(d_x, xtype, S, NSB, T_in, T_sb, nch, d_shift, d_out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lbf_channelize");
     return ok();
 }

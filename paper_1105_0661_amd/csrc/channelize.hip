@@ -1,13 +1,17 @@
 // channelize.hip -- the FFT that splits each subband into channels (Section
-// 4.2 of Mol & Romein): every station's and polarisation's subband time
-// series is cut into consecutive groups of nch samples, and the FFT of a
-// group (forward sign, no window, no scaling) gives one sample of each of the
-// subband's nch channels, lowest frequency first (channel q = FFT bin
-// (q + nch/2) mod nch).
+// 4.2 of Mol & Romein), with the sample-granularity part of delay
+// compensation (Section 3): station s contributes the window of T_sb subband
+// samples starting shift[s] samples into its row (samples outside the row
+// read as zero); every station's and polarisation's window is cut into
+// consecutive groups of nch samples, and the FFT of a group (forward sign,
+// no window function, no scaling) gives one sample of each of the subband's
+// nch channels, lowest frequency first (channel q = FFT bin (q + nch/2) mod
+// nch).
 //
 // One work group per tile of kChTile consecutive samples of one (station,
 // subband) row, both polarisations, in LDS (33 KiB with padding):
-//   1. coalesced loads of the tile's samples, converted to float;
+//   1. coalesced loads of the tile's samples (the station's shifted window),
+//      converted to float;
 //   2. Stockham passes over the tile's kChTile / nch spectra: one radix-2
 //      pass when log2 nch is odd, then radix-4 passes; each pass reads all
 //      its inputs, meets a barrier, and writes in place; the spectra come
@@ -85,19 +89,22 @@ __device__ __forceinline__ void ch_pass(cfl* buf, int nch, int Ns) {
 }
 
 template <int XT>
-__global__ __launch_bounds__(kChThreads) void channelize_kernel(const void* __restrict__ x, int NSB, int Tsb, int nch,
-                                                                int ntile, floatx4* __restrict__ out) {
+__global__ __launch_bounds__(kChThreads) void channelize_kernel(const void* __restrict__ x, int NSB, int Tin, int Tsb,
+                                                                int nch, const int* __restrict__ shift, int ntile,
+                                                                floatx4* __restrict__ out) {
     __shared__ __attribute__((aligned(16))) cfl buf[2 * kChWords];
     const int M = kChTile / nch;                      // spectra per tile
     const int T2 = Tsb / nch;
     const long wg = blockIdx.x;
     const long row = wg / ntile;                      // s NSB + sb
     const int t0 = (int)(wg - row * ntile) * M;
-    const int nvalid = min(M, T2 - t0) * nch;         // samples of the tile inside the row
-    const size_t in0 = (size_t)row * Tsb + (size_t)t0 * nch;
+    const int nvalid = min(M, T2 - t0) * nch;         // samples of the tile inside the window
+    const int s = (int)(row / NSB), sb = (int)(row - (long)s * NSB);
+    const long t_first = (long)t0 * nch + (shift ? shift[s] : 0);   // row sample of the tile's first
     for (int i = threadIdx.x; i < kChTile; i += kChThreads) {
         floatx4 v = {0.f, 0.f, 0.f, 0.f};
-        if (i < nvalid) v = Sample<XT>::load(x, in0 + i);
+        const long t = t_first + i;
+        if (i < nvalid && t >= 0 && t < Tin) v = Sample<XT>::load(x, (size_t)row * Tin + (size_t)t);
         buf[lds_index(i)] = mk(v[0], v[1]);
         buf[kChWords + lds_index(i)] = mk(v[2], v[3]);
     }
@@ -108,7 +115,6 @@ __global__ __launch_bounds__(kChThreads) void channelize_kernel(const void* __re
         Ns = 2;
     }
     for (; Ns < nch; Ns *= 4) ch_pass<4>(buf, nch, Ns);
-    const int s = (int)(row / NSB), sb = (int)(row - (long)s * NSB);
     const size_t C = (size_t)NSB * nch;
     for (int e = threadIdx.x; e < kChTile; e += kChThreads) {
         const int q = e / M, m = e - q * M;
@@ -124,14 +130,18 @@ __global__ __launch_bounds__(kChThreads) void channelize_kernel(const void* __re
     }
 }
 
-hipError_t launch_channelize(const void* x, int xtype, int S, int NSB, int Tsb, int nch, float* out, hipStream_t st) {
+hipError_t launch_channelize(const void* x, int xtype, int S, int NSB, int Tin, int Tsb, int nch, const int* shift,
+                             float* out, hipStream_t st) {
     const int M = kChTile / nch;
     const int ntile = (Tsb / nch + M - 1) / M;
     const dim3 g((unsigned)((size_t)S * NSB * ntile)), b(kChThreads);
     floatx4* o = reinterpret_cast<floatx4*>(out);
-    if (xtype == XT_CI8) hipLaunchKernelGGL(channelize_kernel<XT_CI8>, g, b, 0, st, x, NSB, Tsb, nch, ntile, o);
-    else if (xtype == XT_CI16) hipLaunchKernelGGL(channelize_kernel<XT_CI16>, g, b, 0, st, x, NSB, Tsb, nch, ntile, o);
-    else hipLaunchKernelGGL(channelize_kernel<XT_CF32>, g, b, 0, st, x, NSB, Tsb, nch, ntile, o);
+    if (xtype == XT_CI8)
+        hipLaunchKernelGGL(channelize_kernel<XT_CI8>, g, b, 0, st, x, NSB, Tin, Tsb, nch, shift, ntile, o);
+    else if (xtype == XT_CI16)
+        hipLaunchKernelGGL(channelize_kernel<XT_CI16>, g, b, 0, st, x, NSB, Tin, Tsb, nch, shift, ntile, o);
+    else
+        hipLaunchKernelGGL(channelize_kernel<XT_CF32>, g, b, 0, st, x, NSB, Tin, Tsb, nch, shift, ntile, o);
     return hipGetLastError();
 }
 

@@ -94,7 +94,7 @@ _PROTOS = {
     "lbf_incoherent": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_channelize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_dedisperse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_block_footprint": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.POINTER(BlockSizes)]),
@@ -317,15 +317,20 @@ def incoherent(x, product: int, t_int: int = 1, f_int: int = 1, out=None, stream
     return out
 
 
-def channelize(x, nch: int, out=None, stream=None):
-    """Subband samples x [S][NSB][T_sb][2][2] (int8/int16/float32) -> channels
-    [S][NSB nch][T_sb / nch][2][2] f32, lowest frequency first."""
+def channelize(x, nch: int, t_sb: int = None, shift=None, out=None, stream=None):
+    """Subband samples x [S][NSB][T_in][2][2] (int8/int16/float32) -> channels
+    [S][NSB nch][t_sb / nch][2][2] f32, lowest frequency first.  ``shift``: a
+    device int32 tensor [S] of per-station sample shifts (station s uses row
+    samples shift[s] .. shift[s] + t_sb - 1, zeros outside the row)."""
     torch = _torch()
-    S, NSB, Tsb = x.shape[:3]
+    S, NSB, Tin = x.shape[:3]
+    Tsb = Tin if t_sb is None else t_sb
+    if shift is not None and (shift.dtype != torch.int32 or tuple(shift.shape) != (S,)):
+        raise ValueError("shift must be an int32 tensor of shape (S,)")
     if out is None:
         out = torch.empty((S, NSB * nch, Tsb // nch, 2, 2), dtype=torch.float32, device=x.device)
-    _check(lib().lbf_channelize(_dev_ptr(x, "x"), xtype_of(x), S, NSB, Tsb, nch, _dev_ptr(out, "out"),
-                                _stream(stream)))
+    _check(lib().lbf_channelize(_dev_ptr(x, "x"), xtype_of(x), S, NSB, Tin, Tsb, nch, _dev_ptr(shift, "shift"),
+                                _dev_ptr(out, "out"), _stream(stream)))
     return out
 
 

@@ -69,12 +69,14 @@ def test_other_entry_points_validate_before_device_work():
     assert L.lbf_transpose(1, 2, 3, 4, 1, 16, 2, None) == lbf.E_INVAL          # elem_bytes
     assert L.lbf_transpose(4096, 2, 3, 4, 1, 4, 4100, None) == lbf.E_INVAL     # overlap
     assert L.lbf_incoherent(1, lbf.CI8, 4, 8, 10, lbf.STOKES_I, 4, 1, 1, None) == lbf.E_INVAL
-    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 12, 4096, None) == lbf.E_INVAL     # nch not a power of two
-    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 512, 4096, None) == lbf.E_INVAL    # nch > 256
-    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 60, 16, 4096, None) == lbf.E_INVAL     # T_sb % nch
-    assert L.lbf_channelize(16, 7, 2, 2, 64, 16, 4096, None) == lbf.E_INVAL            # xtype
-    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 16, 24, None) == lbf.E_INVAL       # alignment
-    assert L.lbf_channelize(4096, lbf.CI16, 2, 2, 64, 16, 4096 + 512, None) == lbf.E_INVAL   # overlap
+    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 64, 12, None, 4096, None) == lbf.E_INVAL    # nch not a power of two
+    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 64, 512, None, 4096, None) == lbf.E_INVAL   # nch > 256
+    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 60, 16, None, 4096, None) == lbf.E_INVAL    # T_sb % nch
+    assert L.lbf_channelize(16, 7, 2, 2, 64, 64, 16, None, 4096, None) == lbf.E_INVAL           # xtype
+    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 64, 16, None, 24, None) == lbf.E_INVAL      # alignment
+    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 64, 16, 2, 4096, None) == lbf.E_INVAL       # shift alignment
+    assert L.lbf_channelize(4096, lbf.CI16, 2, 2, 64, 64, 16, None, 4096 + 512, None) == lbf.E_INVAL   # overlap
+    assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 64, 16, 8192, 8192, None) == lbf.E_INVAL    # shift under output
     assert L.lbf_dedisperse(16, 2, 3, 4096, 100, 16, 32, None) == lbf.E_INVAL           # n_fft
     assert L.lbf_dedisperse(16, 2, 3, 1000, 512, 16, 32, None) == lbf.E_INVAL           # T % n_fft
     assert L.lbf_dedisperse(None, 2, 3, 512, 512, 16, 32, None) == lbf.E_INVAL          # NULL

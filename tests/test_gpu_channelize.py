@@ -89,3 +89,30 @@ def test_channelize_one_second_block_sampled():
         want = orc.channelize(xs, nch)                            # [1][nch][768][2]
         got = cplx(out[s:s + 1, sb * nch:(sb + 1) * nch])
         _check(got, want)
+
+
+def test_channelize_with_station_shifts_matches_oracle():
+    """Per-station sample shifts (sample-level delay compensation): windows
+    inside the row, at its end, and hanging over either end (zeros)."""
+    torch = _torch()
+    S, NSB, T_in, T_sb, nch = 5, 2, 1000, 768, 16
+    x = _subbands(S, NSB, T_in, "ci16", 21)
+    shift = np.array([0, 100, 232, -40, 300], np.int32)
+    flush("channelize with shifts %s" % (shift.tolist(),))
+    out = lbf.channelize(to_dev(x), nch, t_sb=T_sb, shift=to_dev(shift))
+    torch.cuda.synchronize()
+    _check(cplx(out), orc.channelize(x, nch, t_sb=T_sb, shift=shift))
+
+
+def test_channelize_shift_aligns_a_delayed_station_bitwise():
+    """Station 1 holds station 0's samples d later; shifted by d, its window
+    holds the same numbers, so its channels are bit for bit station 0's."""
+    torch = _torch()
+    nch, T_sb, d = 64, 4096, 37
+    sig = _subbands(1, 3, T_sb + 64, "ci8", 22)
+    x = np.zeros((2, 3, T_sb + 64, 2, 2), np.int8)
+    x[0] = sig[0]
+    x[1, :, d:] = sig[0, :, :T_sb + 64 - d]
+    out = lbf.channelize(to_dev(x), nch, t_sb=T_sb, shift=to_dev(np.array([0, d], np.int32)))
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], out[1])
