@@ -245,7 +245,7 @@ int lbf_channelize(const void* d_x, int xtype, int S, int NSB, int T_in, int T_s
     if (!d_x || !d_out) return fail(LBF_E_INVAL, "lbf_channelize: NULL device pointer");
     if (((uintptr_t)d_x | (uintptr_t)d_out) & 15) return fail(LBF_E_INVAL, "lbf_channelize: buffers must be 16-byte aligned");
     if (((uintptr_t)d_shift) & 3) return fail(LBF_E_INVAL, "lbf_channelize: shift must be 4-byte aligned");
-    const long long tiles = (T_sb / nch + 2048 / nch - 1) / (2048 / nch);
+    const long long tiles = (T_sb / nch + lbf::kChTile / nch - 1) / (lbf::kChTile / nch);
     if ((long long)S * NSB * tiles > 0x7fffffffLL) return fail(LBF_E_INVAL, "lbf_channelize: too large");
     const size_t in_bytes = (size_t)S * NSB * T_in * (xtype == LBF_CI8 ? 4 : xtype == LBF_CI16 ? 8 : 16);
     const size_t out_bytes = (size_t)S * NSB * T_sb * 16;

@@ -8,8 +8,9 @@
 // nch channels, lowest frequency first (channel q = FFT bin (q + nch/2) mod
 // nch).
 //
-// One work group per tile of kChTile consecutive samples of one (station,
-// subband) row, both polarisations, in LDS (33 KiB with padding):
+// One work group per tile of kChTile (1024) consecutive samples of one
+// (station, subband) row, both polarisations, in LDS (17 KiB with padding,
+// so up to eight groups share a compute unit):
 //   1. coalesced loads of the tile's samples (the station's shifted window),
 //      converted to float;
 //   2. Stockham passes over the tile's kChTile / nch spectra: one radix-2
@@ -26,7 +27,6 @@
 namespace lbf {
 
 constexpr int kChThreads = 256;
-constexpr int kChTile = 2048;                         // samples per polarisation in a tile
 constexpr int kChWords = kChTile + kChTile / 32;      // LDS words per polarisation, padded
 
 // One radix-R (2 or 4) pass of span Ns over every spectrum of the tile.
