@@ -1,14 +1,15 @@
 // dedisperse.hip -- channel-level dedispersion (Section 4.4 of Mol & Romein).
-// Each polarisation's beam voltages are cut into blocks of N = 8^P samples; a
+// Each polarisation's beam voltages are cut into blocks of N (8, 64, 512 or 4096) samples; a
 // block is Fourier transformed, multiplied bin by bin with the channel's
 // precomputed complex chirp weights, and transformed back with a 1/N factor.
 //
 // One work group per (channel, beam, block) keeps both polarisations of the
-// block in LDS (16 N bytes plus padding: 66 KiB at N = 4096) and runs radix-8 Stockham
-// passes.  Pass s (span Ns = 8^s) reads eight elements N/8 apart, turns them by
-// the twiddles exp(-2 pi i (j mod Ns) r / (8 Ns)), takes an 8-point DFT in
-// registers and writes the results Ns apart from (j / Ns) 8 Ns + j mod Ns;
-// after the last pass the spectrum is in natural order, with no bit reversal.
+// block in LDS (16 N bytes plus padding: 66 KiB at N = 4096) and runs Stockham
+// passes of radix R = 16 at N = 4096 (three per transform), 8 otherwise.  Pass
+// s (span Ns = R^s) reads R elements N/R apart, turns them by the twiddles
+// exp(-2 pi i (j mod Ns) r / (R Ns)), takes an R-point DFT in registers and
+// writes the results Ns apart from (j / Ns) R Ns + j mod Ns; after the last
+// pass the spectrum is in natural order, with no bit reversal.
 // Every pass reads all its inputs, meets a barrier, then writes, so one
 // buffer serves in place.  The backward transform is the forward one applied
 // to conjugated data: the last forward pass multiplies by the chirp and
@@ -132,6 +133,108 @@ __device__ __forceinline__ void dd_pass(int Ns, cfl* buf, const floatx4* __restr
     if (DST != 2) __syncthreads();                         // the writes before the next pass reads
 }
 
+// 16-point DFT, forward sign, in place: with x[4a + b], 4-point DFTs over a
+// give Y_b[c]; then Y_b[c] W16^(b c); then 4-point DFTs over b give X[c + 4d]
+__device__ __forceinline__ void dft16(cfl* v) {
+    cfl y[4][4];                                            // y[b][c]
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        cfl a0 = v[b], a1 = v[4 + b], a2 = v[8 + b], a3 = v[12 + b];
+        dft4(a0, a1, a2, a3);
+        y[b][0] = a0; y[b][1] = a1; y[b][2] = a2; y[b][3] = a3;
+    }
+    const float c8 = 0.92387953251128674f, s8 = 0.38268343236508978f, h = 0.70710678118654752f;
+    // W16^(b c) for b c = 1, 2, 3, 2, 4, 6, 3, 6, 9 (cos and sin of pi/8 and pi/4)
+    y[1][1] = cmul(y[1][1], mk(c8, -s8));
+    y[1][2] = cmul(y[1][2], mk(h, -h));
+    y[1][3] = cmul(y[1][3], mk(s8, -c8));
+    y[2][1] = cmul(y[2][1], mk(h, -h));
+    y[2][2] = mk(y[2][2].y, -y[2][2].x);
+    y[2][3] = cmul(y[2][3], mk(-h, -h));
+    y[3][1] = cmul(y[3][1], mk(s8, -c8));
+    y[3][2] = cmul(y[3][2], mk(-h, -h));
+    y[3][3] = cmul(y[3][3], mk(-c8, s8));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        cfl a0 = y[0][c], a1 = y[1][c], a2 = y[2][c], a3 = y[3][c];
+        dft4(a0, a1, a2, a3);
+        v[c] = a0; v[c + 4] = a1; v[c + 8] = a2; v[c + 12] = a3;
+    }
+}
+
+// A radix-16 Stockham pass over both polarisations (N = 4096: one butterfly
+// per thread and polarisation); SRC and DST as in dd_pass.  Twiddles
+// exp(-2 pi i k r / (16 Ns)): w[1] from sincospif, the others as products.
+template <int N, int SRC, int DST>
+__device__ __forceinline__ void dd_pass16(int Ns, cfl* buf, const floatx4* __restrict__ yb, const cfl* __restrict__ hc,
+                                          floatx4* __restrict__ ob) {
+    constexpr int Q = N / 16;
+    static_assert(Q == kDdThreads, "one butterfly per thread and polarisation");
+    cfl v[2][16];
+    const int j = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = j + r * Q;
+        if (SRC == 0) {
+            const floatx4 q = __builtin_nontemporal_load(yb + i);
+            v[0][r] = mk(q[0], q[1]);
+            v[1][r] = mk(q[2], q[3]);
+        } else {
+            v[0][r] = buf[lds_index(i)];
+            v[1][r] = buf[lds_words<N>() + lds_index(i)];
+        }
+    }
+    if (Ns > 1) {
+        float sn, cs;
+        sincospif(-(float)(j % Ns) / (float)(8 * Ns), &sn, &cs);
+        cfl w[16];
+        w[1] = mk(cs, sn);
+        w[2] = cmul(w[1], w[1]);
+        w[4] = cmul(w[2], w[2]);
+        w[8] = cmul(w[4], w[4]);
+        w[3] = cmul(w[1], w[2]);
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+#pragma unroll
+        for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
+#pragma unroll
+        for (int r = 1; r < 16; ++r) {
+            v[0][r] = cmul(v[0][r], w[r]);
+            v[1][r] = cmul(v[1][r], w[r]);
+        }
+    }
+    dft16(v[0]);
+    dft16(v[1]);
+    if (DST != 2) __syncthreads();                         // every read of this pass before any write
+    const int d0 = (j / Ns) * Ns * 16 + j % Ns;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int n = d0 + r * Ns;
+        cfl a = v[0][r], b = v[1][r];
+        if (DST == 1) {
+            const cfl w = hc[n];
+            a = cmul(a, w);
+            b = cmul(b, w);
+            a.y = -a.y;
+            b.y = -b.y;
+        }
+        if (DST == 2) {
+            constexpr float inv = 1.0f / (float)N;          // a power of two: exact
+            floatx4 q;
+            q[0] = a.x * inv;
+            q[1] = -a.y * inv;
+            q[2] = b.x * inv;
+            q[3] = -b.y * inv;
+            __builtin_nontemporal_store(q, ob + n);
+        } else {
+            buf[lds_index(n)] = a;
+            buf[lds_words<N>() + lds_index(n)] = b;
+        }
+    }
+    if (DST != 2) __syncthreads();                         // the writes before the next pass reads
+}
+
 template <int N>
 __global__ __launch_bounds__(kDdThreads) void dedisperse_kernel(const floatx4* __restrict__ y, const cfl* __restrict__ chirp,
                                                                 floatx4* __restrict__ out, int B, int T) {
@@ -145,7 +248,18 @@ __global__ __launch_bounds__(kDdThreads) void dedisperse_kernel(const floatx4* _
     const floatx4* yb = y + base;
     floatx4* ob = out + base;
     const cfl* hc = chirp + (size_t)c * N;
-    constexpr int P = N == 8 ? 1 : N == 64 ? 2 : N == 512 ? 3 : 4;
+    if constexpr (N == 4096) {
+        // three radix-16 passes per transform; the third forward pass applies
+        // the chirp and conjugates, the third backward pass stores
+        dd_pass16<N, 0, 0>(1, buf, yb, hc, ob);
+        dd_pass16<N, 1, 0>(16, buf, yb, hc, ob);
+        dd_pass16<N, 1, 1>(256, buf, yb, hc, ob);
+        dd_pass16<N, 1, 0>(1, buf, yb, hc, ob);
+        dd_pass16<N, 1, 0>(16, buf, yb, hc, ob);
+        dd_pass16<N, 1, 2>(256, buf, yb, hc, ob);
+        return;
+    }
+    constexpr int P = N == 8 ? 1 : N == 64 ? 2 : 3;
     // forward transform; its last pass applies the chirp and conjugates
     int Ns = 1;
     if (P == 1) {
