@@ -8,15 +8,16 @@
 // nch channels, lowest frequency first (channel q = FFT bin (q + nch/2) mod
 // nch).
 //
-// One work group per tile of kChTile (1024) consecutive samples of one
-// (station, subband) row, both polarisations, in LDS (17 KiB with padding,
-// so up to eight groups share a compute unit):
+// One work group per tile of kChTile (2048) consecutive samples of one
+// (station, subband) row, both polarisations, in LDS (33 KiB with padding,
+// so four groups share a compute unit):
 //   1. coalesced loads of the tile's samples (the station's shifted window),
 //      converted to float;
-//   2. Stockham passes over the tile's kChTile / nch spectra: one radix-2
-//      pass when log2 nch is odd, then radix-4 passes; each pass reads all
-//      its inputs, meets a barrier, and writes in place; the spectra come
-//      out in natural order;
+//   2. Stockham passes over the tile's kChTile / nch spectra: radix 16
+//      while four or more bits of nch remain, then radix 4, then radix 2
+//      (two radix-16 passes for 256 channels); each pass reads all its
+//      inputs, meets a barrier, and writes in place; the spectra come out in
+//      natural order;
 //   3. stores in channel order, consecutive lanes on consecutive output
 //      times of one channel: out[s][sb nch + q][t][p], 16 bytes (both
 //      polarisations) per lane.
@@ -29,61 +30,66 @@ namespace lbf {
 constexpr int kChThreads = 256;
 constexpr int kChWords = kChTile + kChTile / 32;      // LDS words per polarisation, padded
 
-// One radix-R (2 or 4) pass of span Ns over every spectrum of the tile.
+// One radix-R (16, 4 or 2) pass of span Ns over every spectrum of the tile;
+// a task is one (butterfly, polarisation).  Twiddles exp(-2 pi i k r / (R Ns)),
+// k = j mod Ns: w[1] from sincospif (exact argument: R Ns is a power of two),
+// the other powers as products built by squaring.
 template <int R>
 __device__ __forceinline__ void ch_pass(cfl* buf, int nch, int Ns) {
-    constexpr int G = kChTile / R;                    // butterflies per polarisation
-    constexpr int BPT = G / kChThreads;               // per thread
+    constexpr int PER_POL = kChTile / R;              // butterflies per polarisation
+    constexpr int TPT = 2 * PER_POL / kChThreads;     // tasks per thread
+    static_assert(TPT >= 1 && 2 * PER_POL % kChThreads == 0, "whole tasks per thread");
     const int nb = nch / R;                           // butterflies per spectrum
-    cfl v[BPT][2][R];
+    cfl v[TPT][R];
 #pragma unroll
-    for (int u = 0; u < BPT; ++u) {
-        const int g = threadIdx.x + kChThreads * u;
+    for (int u = 0; u < TPT; ++u) {
+        const int task = threadIdx.x + kChThreads * u;
+        const int p = task / PER_POL, g = task - p * PER_POL;
         const int m = g / nb, j = g - m * nb;
+        const cfl* pb = buf + p * kChWords;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int n = m * nch + j + r * nb;
-            v[u][0][r] = buf[lds_index(n)];
-            v[u][1][r] = buf[kChWords + lds_index(n)];
-        }
+        for (int r = 0; r < R; ++r) v[u][r] = pb[lds_index(m * nch + j + r * nb)];
         if (Ns > 1) {
-            // exp(-2 pi i k r / (R Ns)), k = j mod Ns; exact argument (R Ns is a power of two)
             float sn, cs;
             sincospif(-2.0f * (float)(j % Ns) / (float)(R * Ns), &sn, &cs);
             cfl w[R];
             w[1] = mk(cs, sn);
-            if (R == 4) {
+            if (R >= 4) {
                 w[2] = cmul(w[1], w[1]);
                 w[3] = cmul(w[1], w[2]);
             }
+            if (R == 16) {
+                w[4] = cmul(w[2], w[2]);
+                w[8] = cmul(w[4], w[4]);
+                w[5] = cmul(w[1], w[4]);
+                w[6] = cmul(w[2], w[4]);
+                w[7] = cmul(w[3], w[4]);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                v[u][0][r] = cmul(v[u][0][r], w[r]);
-                v[u][1][r] = cmul(v[u][1][r], w[r]);
+                for (int r = 9; r < R; ++r) w[r] = cmul(w[r - 8], w[8]);
             }
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], w[r]);
         }
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            if (R == 2) {
-                const cfl a = v[u][p][0], b = v[u][p][1];
-                v[u][p][0] = a + b;
-                v[u][p][1] = a - b;
-            } else {
-                dft4(v[u][p][0], v[u][p][1], v[u][p][2], v[u][p][3]);
-            }
+        if (R == 2) {
+            const cfl a = v[u][0], b = v[u][1];
+            v[u][0] = a + b;
+            v[u][1] = a - b;
+        } else if (R == 4) {
+            dft4(v[u][0], v[u][1], v[u][2], v[u][3]);
+        } else {
+            dft16(v[u]);
         }
     }
     __syncthreads();                                  // every read of this pass before any write
 #pragma unroll
-    for (int u = 0; u < BPT; ++u) {
-        const int g = threadIdx.x + kChThreads * u;
+    for (int u = 0; u < TPT; ++u) {
+        const int task = threadIdx.x + kChThreads * u;
+        const int p = task / PER_POL, g = task - p * PER_POL;
         const int m = g / nb, j = g - m * nb;
         const int d0 = m * nch + (j / Ns) * Ns * R + j % Ns;
+        cfl* pb = buf + p * kChWords;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            buf[lds_index(d0 + r * Ns)] = v[u][0][r];
-            buf[kChWords + lds_index(d0 + r * Ns)] = v[u][1][r];
-        }
+        for (int r = 0; r < R; ++r) pb[lds_index(d0 + r * Ns)] = v[u][r];
     }
     __syncthreads();                                  // the writes before the next pass reads
 }
@@ -109,12 +115,11 @@ __global__ __launch_bounds__(kChThreads) void channelize_kernel(const void* __re
         buf[kChWords + lds_index(i)] = mk(v[2], v[3]);
     }
     __syncthreads();
-    int Ns = 1;
-    if (__builtin_ctz(nch) & 1) {
-        ch_pass<2>(buf, nch, Ns);
-        Ns = 2;
-    }
-    for (; Ns < nch; Ns *= 4) ch_pass<4>(buf, nch, Ns);
+    // radix 16 while four or more bits of nch remain, then 4, then 2
+    int Ns = 1, L = __builtin_ctz(nch);
+    for (; L >= 4; L -= 4, Ns *= 16) ch_pass<16>(buf, nch, Ns);
+    for (; L >= 2; L -= 2, Ns *= 4) ch_pass<4>(buf, nch, Ns);
+    if (L == 1) ch_pass<2>(buf, nch, Ns);
     const size_t C = (size_t)NSB * nch;
     for (int e = threadIdx.x; e < kChTile; e += kChThreads) {
         const int q = e / M, m = e - q * M;

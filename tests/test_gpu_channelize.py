@@ -33,10 +33,11 @@ def _check(got, ref):
             assert relerr(got[s, c], ref[s, c]) <= TOL, (s, c)
 
 
-# (S, NSB, T_sb, nch, xtype): every radix plan (radix-2 first pass for odd
-# log2 nch), tiles cut by the row end, all three input types
+# (S, NSB, T_sb, nch, xtype): every radix plan (radix 16, then 4, then 2:
+# every nch from 2 to 256), tiles cut by the row end, all three input types
 CASES = [(2, 2, 12, 2, "ci16"), (2, 3, 8200, 4, "ci8"), (1, 2, 96, 8, "cf32"), (3, 2, 4144, 16, "ci16"),
-         (2, 2, 640, 64, "ci8"), (2, 1, 2816, 256, "ci16"), (1, 1, 256, 256, "cf32"), (1, 2, 1024, 32, "ci8")]
+         (2, 2, 640, 64, "ci8"), (2, 1, 2816, 256, "ci16"), (1, 1, 256, 256, "cf32"), (1, 2, 1024, 32, "ci8"),
+         (2, 1, 1408, 128, "ci16")]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "S%d_sb%d_T%d_n%d_%s" % c)
