@@ -3,9 +3,9 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this module.  The GPU library never calls it and shares
 no code with it.  The arithmetic lives in ``lbf_oracle.c`` (plain C, FP64);
-this file compiles it with gcc and marshals numpy arrays.  The channeliser and
-dedispersion are written here in numpy (complex128), with numpy's FFT as their
-FFT step.
+this file compiles it with gcc and marshals numpy arrays.  The superstation
+sum, the channeliser and dedispersion are written here in numpy (complex128),
+with numpy's FFT as the FFT step.
 
 Definitions followed (Mol & Romein, "The LOFAR Beam Former"):
 
@@ -19,6 +19,8 @@ Definitions followed (Mol & Romein, "The LOFAR Beam Former"):
 * ``integrate``  -- sums over t_int samples and f_int channels (Sec. 3, Sec. 5.1)
 * ``reorder``    -- final per-beam, per-Stokes order [b][k][t'][c'] (Sec. 4.6)
 * ``incoherent`` -- sum over stations of per-station Stokes (Sec. 3)
+* ``superstation`` -- superstation beam forming (Sec. 4.2): member stations
+  combined, with their weights, into one station signal
 * ``channelize`` -- the FFT that splits each subband into channels (Sec. 4.2):
   nch consecutive subband samples -> nch channels, lowest frequency first
 * ``dedisperse`` -- channel-level dedispersion (Sec. 4.4): per block of
@@ -250,3 +252,21 @@ def channelize(x: np.ndarray, nch: int, t_sb: int | None = None, shift=None) -> 
     spec = np.fft.fft(groups, axis=3)                                           # bin k
     spec = np.fft.fftshift(spec, axes=3)                                        # channel q = bin (q + nch/2) mod nch
     return spec.transpose(0, 1, 3, 2, 4).reshape(S, NSB * nch, Tsb // nch, 2)
+
+
+def superstation(x: np.ndarray, w, groups) -> np.ndarray:
+    """Superstation beam forming (Sec. 4.2: a simplified beam former that
+    combines several stations as if they were one): for each group g of
+    member stations, out[g][c][t][p] = sum over members s of
+    w[c][s] x[s][c][t][p].  x: [S][C][T][2][2] (re, im last); w: complex
+    [C][S], or None for unit weights; groups: a list of member-index lists.
+    Returns complex128 [G][C][T][2]."""
+    x = np.asarray(x)
+    S, C, T = x.shape[:3]
+    xc = x[..., 0].astype(np.float64) + 1j * x[..., 1].astype(np.float64)      # [S][C][T][2]
+    wt = np.ones((C, S), np.complex128) if w is None else np.asarray(w, np.complex128)
+    out = np.zeros((len(groups), C, T, 2), np.complex128)
+    for g, members in enumerate(groups):
+        for s in members:                                                       # the member sum, in member order
+            out[g] += wt[:, s, None, None] * xc[s]
+    return out

@@ -425,3 +425,32 @@ def test_channelize_shift_reads_zero_outside_the_row():
     assert np.abs(got[0, :, 1:]).max() == 0
     neg = orc.channelize(x, 8, t_sb=16, shift=[-8])            # the first group lies before the row
     assert np.abs(neg[0, :, 0]).max() == 0 and abs(neg[0, 4, 1, 0] - 8 * (1 + 1j)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# superstation beam forming (Sec. 4.2)
+# --------------------------------------------------------------------------
+
+def test_superstation_equals_the_beam_former_over_its_members():
+    """With weights toward a direction, a superstation is the tied-array beam
+    of its member stations in that direction: the C oracle's beam former over
+    the members (an independent implementation) gives the same signal."""
+    blk = synth.make_block(6, 2, 1, 4, 32, "ci16", 30.0, tag=(1105, 661, 100))
+    w = orc.block_weights(blk)                                    # [C][B][S]
+    groups = [[0, 2, 3], [5], [1, 4]]
+    got = orc.superstation(blk.x, w[:, 1, :], groups)
+    for g, members in enumerate(groups):
+        want = orc.beamform(np.ascontiguousarray(blk.x[members]), np.ascontiguousarray(w[:, 1:2, members]))
+        assert np.allclose(got[g], want[:, 0], rtol=0, atol=1e-9)
+
+
+def test_superstation_unit_weights_brute_force_and_identity():
+    rng = np.random.default_rng([1105, 661, 101])
+    x = rng.integers(-50, 51, size=(4, 3, 5, 2, 2)).astype(np.int8)
+    got = orc.superstation(x, None, [[1], [0, 3, 2]])
+    xc = x[..., 0].astype(np.float64) + 1j * x[..., 1]
+    assert np.array_equal(got[0], xc[1])                          # one member, unit weight: the station
+    for c in range(3):
+        for t in range(5):
+            for p in range(2):
+                assert got[1, c, t, p] == xc[0, c, t, p] + xc[3, c, t, p] + xc[2, c, t, p]
