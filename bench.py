@@ -164,6 +164,38 @@ def incoherent(lbf, torch, x, steps, warmup, mp):
     return r
 
 
+def superstations(lbf, torch, dev, steps, warmup, mp):
+    """Superstation beam forming on the one-second block's shape: 64 stations
+    (complex int16, 8192 channels, 768 samples) into 8 superstations of 8
+    stations each, unit-modulus weights per (channel, station).  HBM-bound:
+    every station sample read once, every superstation sample written once."""
+    S, C, T, G = 64, 8192, 768, 8
+    gen = torch.Generator(device=dev).manual_seed(1105662)
+    x = torch.randint(-300, 301, (S, C, T, 2, 2), generator=gen, device=dev, dtype=torch.int16)
+    ph = torch.rand((C, S), generator=gen, device=dev, dtype=torch.float64) * 2 * np.pi
+    w = torch.stack([torch.cos(ph), torch.sin(ph)], dim=-1).float().contiguous()
+    groups = [list(range(8 * g, 8 * g + 8)) for g in range(G)]
+    out = torch.empty((G, C, T, 2, 2), dtype=torch.float32, device=dev)
+    nrep = warmup + steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(nrep)]
+    for i in range(nrep):
+        ev[i][0].record()
+        lbf.superstation(x, groups, w, out=out)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(warmup, nrep)]))
+    nbytes = S * C * T * 8 + G * C * T * 16 + C * S * 8
+    gbps = nbytes / (ms / 1e3) / 1e9
+    r = {"workload": "superstation beam forming: 64 stations (complex int16, 8192 channels, 768 samples, 2 pols) "
+                     "-> 8 superstations of 8 stations, weighted",
+         "kernel_ms": ms, "algorithmic_bytes": nbytes, "hbm_GBps": gbps, "bound": "hbm",
+         "frac": gbps / PEAK["hbm_GBps"]}
+    if mp:
+        r["frac_of_measured_copy"] = gbps / mp["hbm_GBps"]
+    del x, w, out
+    return r
+
+
 def channelizer(lbf, torch, dev, steps, warmup, mp):
     """The channeliser ahead of the one-second block: 64 stations x 32
     subbands of 196608 complex int16 samples (1.0066 s at 195 kHz), 256
@@ -537,7 +569,7 @@ def main():
 
     # ---------------- the 488-beam precision block (MFMA-bound) ----------------
     extra = None
-    batch_res = serve_res = unfused_res = inc_res = dd_res = ch_res = None
+    batch_res = serve_res = unfused_res = inc_res = dd_res = ch_res = ss_res = None
     if not a.no_extra and not only:
         unfused_res = unfused(lbf, torch, x, geo, 1024, max(3, a.steps // 4), 1)
         log("unfused chain: %s" % unfused_res)
@@ -547,6 +579,8 @@ def main():
         log("dedispersion: %s" % dd_res)
         ch_res = channelizer(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp)
         log("channeliser: %s" % ch_res)
+        ss_res = superstations(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp)
+        log("superstations: %s" % ss_res)
         b2 = synth.config2(threads=16)
         x2 = torch.from_numpy(b2.x).to(dev)
         geo2 = (torch.from_numpy(b2.station_xyz).to(dev), torch.from_numpy(b2.beam_dir).to(dev),
@@ -651,6 +685,8 @@ def main():
         line["dedispersion"] = dd_res
     if ch_res:
         line["channeliser"] = ch_res
+    if ss_res:
+        line["superstation"] = ss_res
     if batch_res:
         line["batched"] = batch_res
     if serve_res:

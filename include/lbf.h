@@ -184,6 +184,25 @@ int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product,
                    int f_int, float* d_out, void* stream);
 
 /*
+ * Superstation beam forming (Section 4.2: a simplified beam former that
+ * combines several stations as if they were one):
+ *   out[g][c][t][p] = sum over members s of group g of w[c][s] x[s][c][t][p]
+ * summed in member order in FP32.  The members of group g are
+ * members[offsets[g] .. offsets[g+1]) (host arrays, offsets[0] = 0, not
+ * decreasing; a station may belong to several groups).
+ *   d_x   [S][C][T][2] complex of xtype, 16-byte aligned
+ *   d_w   complex f32 [C][S] (e.g. lbf_compute_weights with one direction),
+ *         or NULL for unit weights
+ *   d_out complex f32 [G][C][T][2]: the station-sample layout, so it is a
+ *         CF32 input of lbf_beamform with G stations; must not overlap d_x or d_w
+ * Errors: LBF_E_INVAL for sizes < 1, an unknown xtype, G outside 1..64, more
+ * than 256 members, a member outside 0..S-1, a malformed offsets array, NULL,
+ * misaligned or overlapping buffers.
+ */
+int lbf_superstation(const void* d_x, int xtype, int S, int C, int T, const float* d_w, int G, const int* offsets,
+                     const int* members, float* d_out, void* stream);
+
+/*
  * Channeliser (Section 4.2: an FFT divides each subband into channels), with
  * the sample-granularity part of delay compensation (Section 3: station
  * series are shifted against each other by whole samples; the sub-sample part

@@ -235,6 +235,44 @@ int lbf_incoherent(const void* d_x, int xtype, int S, int C, int T, int product,
     return ok();
 }
 
+int lbf_superstation(const void* d_x, int xtype, int S, int C, int T, const float* d_w, int G, const int* offsets,
+                     const int* members, float* d_out, void* stream) {
+    if (S < 1 || C < 1 || T < 1) return fail(LBF_E_INVAL, "lbf_superstation: sizes must be >= 1");
+    if (xtype < LBF_CI8 || xtype > LBF_CF32) return fail(LBF_E_INVAL, "lbf_superstation: unknown xtype %d", xtype);
+    if (G < 1 || G > lbf::kSsMaxGroups)
+        return fail(LBF_E_INVAL, "lbf_superstation: G=%d outside 1..%d", G, lbf::kSsMaxGroups);
+    if (!offsets || !members) return fail(LBF_E_INVAL, "lbf_superstation: NULL group table");
+    if (!d_x || !d_out) return fail(LBF_E_INVAL, "lbf_superstation: NULL device pointer");
+    if (((uintptr_t)d_x | (uintptr_t)d_out) & 15) return fail(LBF_E_INVAL, "lbf_superstation: buffers must be 16-byte aligned");
+    if (((uintptr_t)d_w) & 7) return fail(LBF_E_INVAL, "lbf_superstation: weights must be 8-byte aligned");
+    lbf::SsGroups gr;
+    gr.G = G;
+    if (offsets[0] != 0) return fail(LBF_E_INVAL, "lbf_superstation: offsets[0] must be 0");
+    for (int g = 0; g <= G; ++g) {
+        if (g > 0 && offsets[g] < offsets[g - 1]) return fail(LBF_E_INVAL, "lbf_superstation: offsets must not decrease");
+        gr.off[g] = offsets[g];
+    }
+    if (offsets[G] > lbf::kSsMaxMembers)
+        return fail(LBF_E_INVAL, "lbf_superstation: %d members, at most %d", offsets[G], lbf::kSsMaxMembers);
+    for (int m = 0; m < offsets[G]; ++m) {
+        if (members[m] < 0 || members[m] >= S)
+            return fail(LBF_E_INVAL, "lbf_superstation: member %d is station %d, outside 0..%d", m, members[m], S - 1);
+        gr.mem[m] = members[m];
+    }
+    if ((long long)G * C * ((T + 255) / 256) > 0x7fffffffLL) return fail(LBF_E_INVAL, "lbf_superstation: too large");
+    const size_t in_bytes = (size_t)S * C * T * (xtype == LBF_CI8 ? 4 : xtype == LBF_CI16 ? 8 : 16);
+    const size_t out_bytes = (size_t)G * C * T * 16;
+    const char* a = (const char*)d_x;
+    const char* o = (const char*)d_out;
+    const char* wv = (const char*)d_w;
+    if (a < o + out_bytes && o < a + in_bytes) return fail(LBF_E_INVAL, "lbf_superstation: input and output overlap");
+    if (wv && wv < o + out_bytes && o < wv + (size_t)C * S * 8)
+        return fail(LBF_E_INVAL, "lbf_superstation: weights and output overlap");
+    hipError_t e = lbf::launch_superstation(d_x, xtype, S, C, T, d_w, gr, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_superstation");
+    return ok();
+}
+
 int lbf_channelize(const void* d_x, int xtype, int S, int NSB, int T_in, int T_sb, int nch, const int* d_shift,
                    float* d_out, void* stream) {
     if (S < 1 || NSB < 1 || T_in < 1 || T_sb < 1) return fail(LBF_E_INVAL, "lbf_channelize: sizes must be >= 1");

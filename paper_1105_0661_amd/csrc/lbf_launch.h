@@ -27,6 +27,15 @@ hipError_t launch_probe(int kind, int iters, const void* src, void* dst, size_t 
 hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, int ldb, float* out, hipStream_t st);
 hipError_t launch_incoherent(const void* x, int xtype, int S, int C, int T, int product, int t_int, int f_int,
                              float* out, hipStream_t st);
+// superstation groups: member station indices of group g are mem[off[g] .. off[g + 1])
+constexpr int kSsMaxGroups = 64, kSsMaxMembers = 256;
+struct SsGroups {
+    int G;
+    int off[kSsMaxGroups + 1];
+    int mem[kSsMaxMembers];
+};
+hipError_t launch_superstation(const void* x, int xtype, int S, int C, int T, const float* w, const SsGroups& gr,
+                               float* out, hipStream_t st);
 constexpr int kChTile = 2048;   // channeliser: subband samples per polarisation in one work group's tile
 hipError_t launch_channelize(const void* x, int xtype, int S, int NSB, int Tin, int Tsb, int nch, const int* shift,
                              float* out, hipStream_t st);

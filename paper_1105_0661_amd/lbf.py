@@ -93,6 +93,9 @@ _PROTOS = {
                                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_incoherent": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbf_superstation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_channelize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_dedisperse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -314,6 +317,28 @@ def incoherent(x, product: int, t_int: int = 1, f_int: int = 1, out=None, stream
         out = torch.empty((n_stokes(product), T // t_int, C // f_int), dtype=torch.float32, device=x.device)
     _check(lib().lbf_incoherent(_dev_ptr(x, "x"), xtype_of(x), S, C, T, product, t_int, f_int,
                                 _dev_ptr(out, "out"), _stream(stream)))
+    return out
+
+
+def superstation(x, groups, w=None, out=None, stream=None):
+    """Superstations [G][C][T][2][2] f32 from stations x [S][C][T][2][2]:
+    group g sums its member stations ``groups[g]`` (a list of station
+    indices), each weighted by w [C][S][2] f32 (None: unit weights)."""
+    torch = _torch()
+    S, C, T = x.shape[:3]
+    G = len(groups)
+    offs = [0]
+    for members in groups:
+        offs.append(offs[-1] + len(members))
+    off_arr = (ctypes.c_int * (G + 1))(*offs)
+    flat = [int(s) for members in groups for s in members]
+    mem_arr = (ctypes.c_int * max(1, len(flat)))(*flat)
+    if w is not None and tuple(w.shape) != (C, S, 2):
+        raise ValueError("w must be [C][S][2]")
+    if out is None:
+        out = torch.empty((G, C, T, 2, 2), dtype=torch.float32, device=x.device)
+    _check(lib().lbf_superstation(_dev_ptr(x, "x"), xtype_of(x), S, C, T, _dev_ptr(w, "w"), G, off_arr, mem_arr,
+                                  _dev_ptr(out, "out"), _stream(stream)))
     return out
 
 

@@ -77,6 +77,13 @@ def test_other_entry_points_validate_before_device_work():
     assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 64, 16, 2, 4096, None) == lbf.E_INVAL       # shift alignment
     assert L.lbf_channelize(4096, lbf.CI16, 2, 2, 64, 64, 16, None, 4096 + 512, None) == lbf.E_INVAL   # overlap
     assert L.lbf_channelize(16, lbf.CI16, 2, 2, 64, 64, 16, 8192, 8192, None) == lbf.E_INVAL    # shift under output
+    I = ctypes.c_int
+    off, mem = (I * 3)(0, 2, 3), (I * 3)(0, 1, 2)
+    assert L.lbf_superstation(16, lbf.CI16, 2, 4, 8, None, 2, off, mem, 4096, None) == lbf.E_INVAL    # member 2 >= S
+    assert L.lbf_superstation(16, lbf.CI16, 3, 4, 8, None, 65, off, mem, 4096, None) == lbf.E_INVAL   # G > 64
+    assert L.lbf_superstation(16, lbf.CI16, 3, 4, 8, None, 2, (I * 3)(0, 2, 1), mem, 4096, None) == lbf.E_INVAL
+    assert L.lbf_superstation(16, lbf.CI16, 3, 4, 8, None, 2, off, mem, 4100, None) == lbf.E_INVAL    # alignment
+    assert L.lbf_superstation(4096, lbf.CI16, 3, 4, 8, None, 2, off, mem, 4096 + 64, None) == lbf.E_INVAL   # overlap
     assert L.lbf_dedisperse(16, 2, 3, 4096, 100, 16, 32, None) == lbf.E_INVAL           # n_fft
     assert L.lbf_dedisperse(16, 2, 3, 1000, 512, 16, 32, None) == lbf.E_INVAL           # T % n_fft
     assert L.lbf_dedisperse(None, 2, 3, 512, 512, 16, 32, None) == lbf.E_INVAL          # NULL
