@@ -12,7 +12,8 @@
 // (station, subband) row, both polarisations, in LDS (33 KiB with padding,
 // so four groups share a compute unit):
 //   1. coalesced loads of the tile's samples (the station's shifted window),
-//      converted to float;
+//      16-byte vectors of 1, 2 or 4 samples when the window is aligned and
+//      inside the row, single samples otherwise; converted to float;
 //   2. Stockham passes over the tile's kChTile / nch spectra: radix 16
 //      while four or more bits of nch remain, then radix 4, then radix 2
 //      (two radix-16 passes for 256 channels); each pass reads all its
@@ -94,6 +95,32 @@ __device__ __forceinline__ void ch_pass(cfl* buf, int nch, int Ns) {
     __syncthreads();                                  // the writes before the next pass reads
 }
 
+// The samples of one 16-byte vector, each as (x re, x im, y re, y im):
+// 4 complex int8 samples, 2 complex int16 samples or 1 complex float sample
+template <int XT>
+__device__ __forceinline__ void vec_samples(const intx4 q, float (*f)[4]) {
+    if constexpr (XT == XT_CI8) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            f[h][0] = (float)((q[h] << 24) >> 24);
+            f[h][1] = (float)((q[h] << 16) >> 24);
+            f[h][2] = (float)((q[h] << 8) >> 24);
+            f[h][3] = (float)(q[h] >> 24);
+        }
+    } else if constexpr (XT == XT_CI16) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            f[h][0] = (float)((q[2 * h] << 16) >> 16);
+            f[h][1] = (float)(q[2 * h] >> 16);
+            f[h][2] = (float)((q[2 * h + 1] << 16) >> 16);
+            f[h][3] = (float)(q[2 * h + 1] >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[0][k] = __int_as_float(q[k]);
+    }
+}
+
 template <int XT>
 __global__ __launch_bounds__(kChThreads) void channelize_kernel(const void* __restrict__ x, int NSB, int Tin, int Tsb,
                                                                 int nch, const int* __restrict__ shift, int ntile,
@@ -107,12 +134,30 @@ __global__ __launch_bounds__(kChThreads) void channelize_kernel(const void* __re
     const int nvalid = min(M, T2 - t0) * nch;         // samples of the tile inside the window
     const int s = (int)(row / NSB), sb = (int)(row - (long)s * NSB);
     const long t_first = (long)t0 * nch + (shift ? shift[s] : 0);   // row sample of the tile's first
-    for (int i = threadIdx.x; i < kChTile; i += kChThreads) {
-        floatx4 v = {0.f, 0.f, 0.f, 0.f};
-        const long t = t_first + i;
-        if (i < nvalid && t >= 0 && t < Tin) v = Sample<XT>::load(x, (size_t)row * Tin + (size_t)t);
-        buf[lds_index(i)] = mk(v[0], v[1]);
-        buf[kChWords + lds_index(i)] = mk(v[2], v[3]);
+    constexpr int P = 16 / Sample<XT>::bytes;           // samples per 16-byte vector
+    const size_t r0 = (size_t)row * Tin;
+    if (t_first >= 0 && t_first + nvalid <= Tin && (r0 + t_first) % P == 0 && nvalid % P == 0) {
+        // the window lies inside the row on a 16-byte boundary: P samples per lane and load
+        const intx4* xv = reinterpret_cast<const intx4*>(static_cast<const char*>(x) + (r0 + t_first) * Sample<XT>::bytes);
+        for (int iv = threadIdx.x; iv < kChTile / P; iv += kChThreads) {
+            intx4 q = {0, 0, 0, 0};
+            if (iv * P < nvalid) q = __builtin_nontemporal_load(xv + iv);
+            float f[P][4];
+            vec_samples<XT>(q, f);
+#pragma unroll
+            for (int h = 0; h < P; ++h) {
+                buf[lds_index(iv * P + h)] = mk(f[h][0], f[h][1]);
+                buf[kChWords + lds_index(iv * P + h)] = mk(f[h][2], f[h][3]);
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < kChTile; i += kChThreads) {
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            const long t = t_first + i;
+            if (i < nvalid && t >= 0 && t < Tin) v = Sample<XT>::load(x, r0 + (size_t)t);
+            buf[lds_index(i)] = mk(v[0], v[1]);
+            buf[kChWords + lds_index(i)] = mk(v[2], v[3]);
+        }
     }
     __syncthreads();
     // radix 16 while four or more bits of nch remain, then 4, then 2
