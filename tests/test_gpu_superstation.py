@@ -32,9 +32,11 @@ def _weights(C, S, seed):
 
 
 # (S, C, T, xtype, groups): single members, a station in two groups, ragged
-# T (not a multiple of the 256-sample chunk)
+# T (not a multiple of the work group's samples); T a multiple of the
+# samples per 16-byte vector (vector kernel) and not (one sample per thread)
 CASES = [(6, 3, 300, "ci16", [[0, 1, 2], [3], [4, 5, 0]]), (9, 2, 64, "ci8", [[8, 7, 6, 5, 4, 3, 2, 1, 0]]),
-         (4, 5, 513, "cf32", [[1, 3], [2], [0, 2]])]
+         (4, 5, 513, "cf32", [[1, 3], [2], [0, 2]]), (5, 2, 301, "ci16", [[4, 0], [1, 2, 3]]),
+         (3, 2, 66, "ci8", [[2, 1], [0]])]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "S%d_C%d_T%d_%s_G%d" % (c[0], c[1], c[2], c[3], len(c[4])))
