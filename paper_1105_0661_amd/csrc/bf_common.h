@@ -640,8 +640,8 @@ LBF_INLINE WaveTiles wave_tiles(int wave, int T, int t_int) {
 // (work items of 256 beams), else two (items of 128 beams).
 __host__ __device__ inline int fast_h_streams(const BlockDesc& d) { return d.b1 - d.b0 > 128 ? 1 : 2; }
 
-// K-steps of 8 stations of the fast FP16/BF16 worker: 4, 6 or 8
-__host__ __device__ inline int fast_h_ksteps(int S) { return S <= 32 ? 4 : S <= 48 ? 6 : 8; }
+// K-steps of 8 stations of the fast FP16/BF16 worker: 4 to 8, the fewest that hold the stations (at least 4)
+__host__ __device__ inline int fast_h_ksteps(int S) { return S <= 32 ? 4 : (S + 7) / 8; }
 
 // A block whose beams beyond the last whole 256-beam group number at most 128
 // is taken in two parts: the 256-beam groups, and the rest as 128-beam items

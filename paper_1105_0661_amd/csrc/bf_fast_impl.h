@@ -51,7 +51,9 @@ inline void launch_h_ns(const BlockDesc& d, int nbg, int n, hipStream_t st) {
     const dim3 g(n), b(kThreadsH);
     switch (fast_h_ksteps(d.S)) {
         case 4: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4, NS>), g, b, 0, st, d, nbg, n); break;
+        case 5: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 5, NS>), g, b, 0, st, d, nbg, n); break;
         case 6: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 6, NS>), g, b, 0, st, d, nbg, n); break;
+        case 7: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 7, NS>), g, b, 0, st, d, nbg, n); break;
         default: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8, NS>), g, b, 0, st, d, nbg, n); break;
     }
 }

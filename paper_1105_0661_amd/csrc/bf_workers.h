@@ -211,7 +211,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
 }
 
 // FP16/BF16 operands (MFMA 32x32x16: 8 stations per K-step, NK K-steps:
-// 4, 6 or 8, the fewest that hold the block's stations).
+// 4 to 8, the fewest that hold the block's stations).
 //
 // A work group of 8 waves (two per SIMD) takes one channel and NBT = 8/NS
 // beam tiles of 32 beams; its tiles of 32 samples are split into NS streams.

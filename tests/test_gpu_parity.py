@@ -113,11 +113,12 @@ def test_single_station_zero_delay_is_identity():
 
 
 @pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
-@pytest.mark.parametrize("S,T", [(1, 32), (7, 33), (24, 96), (33, 100), (41, 72), (48, 64), (64, 64)])
+@pytest.mark.parametrize("S,T", [(1, 32), (7, 33), (24, 96), (33, 100), (38, 64), (41, 72), (48, 64), (53, 80),
+                                 (56, 40), (64, 64)])
 def test_fast_path_station_and_sample_edges(ctype, S, T):
     # the fast workers pad stations to 8-station groups (zero beyond S; the
-    # FP16/BF16 one to 32, 48 or 64 stations) and clamp the rows of a ragged
-    # last sample tile
+    # FP16/BF16 one to 32, 40, 48, 56 or 64 stations) and clamp the rows of a
+    # ragged last sample tile
     torch = _torch()
     xt = "ci8" if ctype == lbf.BF16 else "ci16"
     blk = synth.make_block(S, 37, 1, 3, T, xt, 16.0 if xt == "ci8" else 40.0, tag=(1105, 661, 59))
@@ -319,14 +320,15 @@ def test_incoherent_beam_matches_oracle(case):
 def test_batch_equals_single_launches_bitwise(ctype):
     torch = _torch()
     # batch-kernel blocks (t_int 16, no channel integration): one and two
-    # sample streams (more / at most 128 beams), 4, 6 and 8 K-steps, ragged
+    # sample streams (more / at most 128 beams), 4 to 8 K-steps, ragged
     # T, a beam tail split off a 256-beam group, two blocks of one worker
     # variant in one launch; the rest run through their own launches
     specs = [(24, 17, 2, 4, 64, "ci8", lbf.STOKES_I, 16, 1), (29, 130, 2, 3, 208, "ci8", lbf.STOKES_IQUV, 16, 1),
              (33, 200, 1, 4, 112, "ci16", lbf.STOKES_I, 16, 1), (64, 40, 2, 4, 176, "ci16", lbf.STOKES_IQUV, 16, 1),
              (40, 150, 1, 8, 96, "ci16", lbf.STOKES_IQUV, 16, 2), (45, 300, 1, 3, 64, "ci8", lbf.STOKES_IQUV, 16, 1),
              (64, 33, 3, 2, 32, "ci8", lbf.STOKES_IQUV, 32, 1), (31, 1, 1, 5, 48, "ci16", lbf.STOKES_I, 4, 1),
-             (26, 20, 1, 3, 80, "ci8", lbf.STOKES_I, 16, 1)]
+             (26, 20, 1, 3, 80, "ci8", lbf.STOKES_I, 16, 1), (53, 140, 1, 3, 48, "ci16", lbf.STOKES_IQUV, 16, 1),
+             (38, 60, 2, 2, 64, "ci8", lbf.STOKES_I, 16, 1)]
     items, singles, refs = [], [], []
     for i, (S, B, nsb, nch, T, xt, prod, ti, fi) in enumerate(specs):
         blk = synth.make_block(S, B, nsb, nch, T, xt, 16.0 if xt == "ci8" else 40.0, tag=(1105, 661, 60 + i))
