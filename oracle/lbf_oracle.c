@@ -8,9 +8,11 @@
  * What it computes follows Mol & Romein, "The LOFAR Beam Former: Implementation
  * and Performance Analysis":
  *
- *   delays     tau[b][s] = p_s . (u_b - u_ref) / c0          (Sec. 3, Sec. 4.3:
+ *   delays     tau[b][s] = p_s . (u_b - u_ref) / c0 - delta_s  (Sec. 3, Sec. 4.3:
  *              weights depend on station location, channel frequency and
- *              tied-array beam coordinates)
+ *              tied-array beam coordinates; delta_s is the residual delay of
+ *              station s left after its series was shifted by whole samples,
+ *              Sec. 3, which the weights' phase compensates)
  *   weights    w[c][b][s] = exp(-2 pi i frac(f_c tau[b][s]))  (Sec. 3: the phase
  *              of each sample is shifted by a complex multiplication; the
  *              fractional turn is taken in FP64 because f*tau spans many turns)
@@ -60,8 +62,12 @@ static void lbfo_sample(const void* x, int xtype, size_t idx, double* re, double
     }
 }
 
-/* tau[b][s] = p_s . (u_b - u_ref) / c0 ; ref == NULL means u_ref = 0 */
-void lbfo_delays(const double* pos, int S, const double* dir, int B, const double* ref, double* tau)
+/* tau[b][s] = p_s . (u_b - u_ref) / c0 - resid[s] ; ref == NULL means u_ref = 0,
+ * resid == NULL means no residual delays.  A station whose signal arrives
+ * resid[s] seconds late needs its phase advanced by 2 pi f resid[s]: the
+ * weight exp(-2 pi i f tau) does that with the residual subtracted. */
+void lbfo_delays(const double* pos, int S, const double* dir, int B, const double* ref, const double* resid,
+                 double* tau)
 {
     for (int b = 0; b < B; ++b) {
         double d[3];
@@ -69,7 +75,7 @@ void lbfo_delays(const double* pos, int S, const double* dir, int B, const doubl
             d[k] = dir[3 * b + k] - (ref ? ref[k] : 0.0);
         for (int s = 0; s < S; ++s) {
             double proj = pos[3 * s + 0] * d[0] + pos[3 * s + 1] * d[1] + pos[3 * s + 2] * d[2];
-            tau[(size_t)b * S + s] = proj / LBFO_C0;
+            tau[(size_t)b * S + s] = proj / LBFO_C0 - (resid ? resid[s] : 0.0);
         }
     }
 }
@@ -242,14 +248,14 @@ static void* lbfo_worker(void* arg)
 /* out: K > 0 -> [B][K][T/t_int][C/f_int] doubles; K == 0 -> voltages
  * [B][2][T][C] complex (f_int must then be 1).  Returns 0, or -1 on bad args. */
 int lbfo_pipeline(const void* x, int xtype, int S, int C, int T, const double* pos,
-                  const double* dir, int B, const double* ref, const double* freq,
+                  const double* dir, int B, const double* ref, const double* resid, const double* freq,
                   int K, int t_int, int f_int, int nthreads, double* out)
 {
     if (S < 1 || C < 1 || T < 1 || B < 1 || t_int < 1 || f_int < 1) return -1;
     if (C % f_int || (K && T % t_int) || (K == 0 && f_int != 1)) return -1;
     if (K != 0 && K != 1 && K != 4) return -1;
     double* tau = (double*)malloc(sizeof(double) * (size_t)B * S);
-    lbfo_delays(pos, S, dir, B, ref, tau);
+    lbfo_delays(pos, S, dir, B, ref, resid, tau);
     int G = C / f_int;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > G) nthreads = G;

@@ -9,8 +9,13 @@ with numpy's FFT as the FFT step.
 
 Definitions followed (Mol & Romein, "The LOFAR Beam Former"):
 
-* ``delays``     -- tau[b][s] = p_s . (u_b - u_ref) / c0 (Sec. 3; Sec. 4.3:
-  weights depend on station location, channel frequency and beam coordinates)
+* ``delays``     -- tau[b][s] = p_s . (u_b - u_ref) / c0 - delta_s (Sec. 3; Sec. 4.3:
+  weights depend on station location, channel frequency and beam coordinates;
+  delta_s is an optional per-station residual delay, see ``phase_correct``)
+* ``phase_correct`` -- sub-sample delay compensation (Sec. 3): after the
+  station series are shifted by whole samples, each sample is multiplied by a
+  complex phase that removes the station's remaining delay at the channel's
+  frequency
 * ``weights``    -- w[c][b][s] = exp(-2 pi i frac(f_c tau)) (Sec. 3, phase shift
   by a complex multiplication per sample)
 * ``beamform``   -- y[c][b][t][p] = sum_s w[c][b][s] x[s][c][t][p] (Sec. 1,
@@ -70,14 +75,14 @@ def _load():
             build()
             lib = ctypes.CDLL(_SO)
             vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
-            lib.lbfo_delays.argtypes = [_dp, i, _dp, i, vp, _dp]
+            lib.lbfo_delays.argtypes = [_dp, i, _dp, i, vp, vp, _dp]
             lib.lbfo_weights.argtypes = [_dp, i, i, _dp, i, _dp]
             lib.lbfo_beamform.argtypes = [vp, i, i, i, i, i, i, _dp, i, _dp]
             lib.lbfo_stokes.argtypes = [_dp, i, i, i, _dp]
             lib.lbfo_integrate.argtypes = [_dp, i, i, i, i, i, i, _dp]
             lib.lbfo_reorder.argtypes = [_dp, i, i, i, i, i, _dp]
             lib.lbfo_incoherent.argtypes = [vp, i, i, i, i, i, i, i, _dp]
-            lib.lbfo_pipeline.argtypes = [vp, i, i, i, i, _dp, _dp, i, vp, _dp, i, i, i, i, _dp]
+            lib.lbfo_pipeline.argtypes = [vp, i, i, i, i, _dp, _dp, i, vp, vp, _dp, i, i, i, i, _dp]
             lib.lbfo_pipeline.restype = i
             for f in ("lbfo_delays", "lbfo_weights", "lbfo_beamform", "lbfo_stokes", "lbfo_integrate",
                       "lbfo_reorder", "lbfo_incoherent"):
@@ -100,13 +105,19 @@ def _xtype_of(x: np.ndarray) -> int:
     raise TypeError("station samples must be int8, int16 or float32, got %s" % x.dtype)
 
 
-def delays(pos, dirs, ref=None) -> np.ndarray:
-    """tau[b][s] in seconds."""
+def delays(pos, dirs, ref=None, resid=None) -> np.ndarray:
+    """tau[b][s] in seconds; ``resid`` [S]: residual delays (seconds, positive
+    for a station whose signal arrives late), subtracted from every beam's
+    delay of that station."""
     pos, dirs = _f64(pos), _f64(dirs)
     S, B = pos.shape[0], dirs.shape[0]
     tau = np.empty((B, S))
     refp = None if ref is None else _f64(ref)
-    _load().lbfo_delays(pos, S, dirs, B, None if refp is None else refp.ctypes.data, tau)
+    rp = None if resid is None else _f64(resid)
+    if rp is not None and rp.shape != (S,):
+        raise ValueError("resid must hold one delay per station")
+    _load().lbfo_delays(pos, S, dirs, B, None if refp is None else refp.ctypes.data,
+                        None if rp is None else rp.ctypes.data, tau)
     return tau
 
 
@@ -176,26 +187,54 @@ def incoherent(x: np.ndarray, K: int, t_int: int, f_int: int) -> np.ndarray:
 
 
 def pipeline(x: np.ndarray, pos, dirs, ref, freq, K: int, t_int: int = 1, f_int: int = 1,
-             nthreads: int = 1) -> np.ndarray:
+             nthreads: int = 1, resid=None) -> np.ndarray:
     """Whole chain: out[B][K][T/t_int][C/f_int] (K in {1, 4}) or, for K == 0,
-    voltages [B][2][T][C] complex128."""
+    voltages [B][2][T][C] complex128.  ``resid``: per-station residual delays
+    folded into the weights (see ``delays``)."""
     x = np.ascontiguousarray(x)
     S, C, T = x.shape[:3]
     pos, dirs, freq = _f64(pos), _f64(dirs), _f64(freq)
     B = dirs.shape[0]
     refp = None if ref is None else _f64(ref)
+    rp = None if resid is None else _f64(resid)
+    if rp is not None and rp.shape != (S,):
+        raise ValueError("resid must hold one delay per station")
     if K == 0:
         out = np.empty((B, 2, T, C, 2))
     else:
         out = np.empty((B, K, T // t_int, C // f_int))
     rc = _load().lbfo_pipeline(x.ctypes.data, _xtype_of(x), S, C, T, pos, dirs, B,
-                               None if refp is None else refp.ctypes.data, freq, K, t_int, f_int,
+                               None if refp is None else refp.ctypes.data,
+                               None if rp is None else rp.ctypes.data, freq, K, t_int, f_int,
                                nthreads, out)
     if rc != 0:
         raise ValueError("oracle pipeline rejected its arguments")
     if K == 0:
         return out[..., 0] + 1j * out[..., 1]
     return out
+
+
+def phase_correct(x: np.ndarray, freq, resid) -> np.ndarray:
+    """Sub-sample delay compensation (Sec. 3): once station series have been
+    shifted against each other by whole samples, the delay that remains,
+    resid[s] seconds (positive: station s's signal arrives late), is removed
+    by one complex multiplication per sample that advances its phase at the
+    sample's frequency:
+        out[s][c][t][p] = x[s][c][t][p] * exp(+2 pi i frac(f_c resid[s])).
+    The fractional turn is taken in FP64 as for the weights.  x: channelised
+    samples [S][C][T][2] (complex) or [S][C][T][2][2] (re, im last); freq [C]
+    Hz; resid [S] s.  Returns complex128 [S][C][T][2]."""
+    x = np.asarray(x)
+    if not np.iscomplexobj(x):
+        x = x[..., 0].astype(np.float64) + 1j * x[..., 1].astype(np.float64)
+    freq, resid = _f64(freq), _f64(resid)
+    S, C = x.shape[:2]
+    if freq.shape != (C,) or resid.shape != (S,):
+        raise ValueError("freq must be [C] and resid [S]")
+    m = resid[:, None] * freq[None, :]                        # turns, [S][C]
+    r = m - np.rint(m)
+    rot = np.cos(2.0 * np.pi * r) + 1j * np.sin(2.0 * np.pi * r)
+    return x.astype(np.complex128) * rot[:, :, None, None]
 
 
 def block_weights(blk, use_ref: bool = True) -> np.ndarray:

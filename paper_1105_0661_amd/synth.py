@@ -18,8 +18,8 @@ The shapes follow the paper's data model:
 Geometry is a local East-North-Up frame: station positions in metres,
 directions as unit vectors ``(l, m, n)`` with ``n = sqrt(1 - l^2 - m^2)``.
 A tone from direction ``u`` reaches station ``s`` with the phase of a plane
-wave, ``exp(+2 pi i f p_s.(u - u_ref) / c0)`` (Section 3: signals from a source
-reach different antennas at different times).
+wave, ``exp(+2 pi i f p_s.(u - u_ref) / c0)``: the geometric delay of Section 3,
+seen as a phase at the channel's frequency.
 
 Randomness: geometry and tones come from ``default_rng([1105, 661, tag])``;
 the noise of station ``s`` in subband ``sb`` from
@@ -133,6 +133,45 @@ def channel_freqs(nsb: int, nch: int, base_hz: float = BASE_HZ) -> np.ndarray:
     sb = np.arange(nsb, dtype=np.float64)[:, None]
     k = np.arange(nch, dtype=np.float64)[None, :]
     return (base_hz + sb * SUBBAND_HZ + k * (SUBBAND_HZ / nch)).reshape(-1)
+
+
+def centred_channel_freqs(nsb: int, nch: int, first_subband: int = 768) -> np.ndarray:
+    """Channel frequencies of subbands centred on whole multiples of the
+    subband width, as a station's polyphase filter bank forms them (subband k
+    centred at k * 195312.5 Hz): f[sb*nch + q] = (first_subband + sb) *
+    195312.5 + (q - nch/2) * 195312.5 / nch, so channel nch/2 sits at the
+    subband's centre (FFT bin 0 of the channeliser)."""
+    sb = np.arange(nsb, dtype=np.float64)[:, None]
+    q = np.arange(nch, dtype=np.float64)[None, :]
+    return ((first_subband + sb) * SUBBAND_HZ + (q - nch / 2) * (SUBBAND_HZ / nch)).reshape(-1)
+
+
+def delayed_subband_tones(S: int, nsb: int, nch: int, T_in: int, delay_samples, tones, xtype: str = "ci16",
+                          first_subband: int = 768) -> np.ndarray:
+    """Subband samples [S][nsb][T_in][2][2] of stations that all receive the
+    same tones, station s ``delay_samples[s]`` subband samples late (any real
+    number).  ``tones``: (subband, channel q, amplitude, (phase X, phase Y))
+    tuples; the tone sits at the centre of channel q, nu = (q - nch/2) / nch
+    cycles per subband sample from the subband's centre f_mix, i.e. at sky
+    frequency f = f_mix + nu * 195312.5 Hz (``centred_channel_freqs``).  The
+    station mixes its delayed signal down by f_mix and samples it every
+    1/195312.5 s, which gives
+        x_s[sb][n][p] = sum_tones A exp(i (2 pi (nu n - f D_s) + phase_p)),
+    D_s = delay_samples[s] / 195312.5 s; quantised with clip(rint(.))."""
+    d = np.asarray(delay_samples, dtype=np.float64)
+    if d.shape != (S,):
+        raise ValueError("one delay per station")
+    n = np.arange(T_in, dtype=np.float64)
+    v = np.zeros((S, nsb, T_in, 2), np.complex128)
+    for sb, q, amp, ph in tones:
+        nu = (q - nch / 2) / nch
+        f = (first_subband + sb) * SUBBAND_HZ + nu * SUBBAND_HZ
+        D = d / SUBBAND_HZ                                              # seconds
+        arg = 2.0 * np.pi * (nu * n[None, :] - (f * D)[:, None])       # [S][T_in]
+        for p in range(2):
+            v[:, sb, :, p] += amp * np.exp(1j * (arg + ph[p]))
+    out = np.stack([v.real, v.imag], axis=-1)
+    return _quantise(out, xtype)
 
 
 def samples_per_block(seconds: float, nch: int) -> int:

@@ -454,3 +454,91 @@ def test_superstation_unit_weights_brute_force_and_identity():
         for t in range(5):
             for p in range(2):
                 assert got[1, c, t, p] == xc[0, c, t, p] + xc[3, c, t, p] + xc[2, c, t, p]
+
+
+# --------------------------------------------------------------------------
+# delay compensation (Sec. 3): whole-sample shift, then a per-sample phase
+# --------------------------------------------------------------------------
+
+def _einsum_beams(w, xc):
+    """Independent library routine: y[c][b][t][p] = sum_s w[c][b][s] x[s][c][t][p]."""
+    return np.einsum("cbs,sctp->cbtp", w, xc)
+
+
+def test_residual_delay_is_taken_off_every_beams_delay():
+    rng = np.random.default_rng([1105, 661, 102])
+    blk = synth.make_block(5, 3, 1, 4, 16, generate=False, tag=(1105, 661, 102))
+    resid = rng.uniform(-3e-6, 3e-6, size=5)
+    tau0 = orc.delays(blk.station_xyz, blk.beam_dir, blk.ref_dir)
+    tau1 = orc.delays(blk.station_xyz, blk.beam_dir, blk.ref_dir, resid=resid)
+    assert np.allclose(tau1, tau0 - resid[None, :], rtol=0, atol=1e-21)
+    # a station exactly one period of channel c late needs no correction there
+    f = synth.centred_channel_freqs(1, 4)
+    late = np.zeros(5)
+    late[2] = 1.0 / f[1]
+    w = orc.weights(orc.delays(blk.station_xyz, blk.beam_dir, blk.ref_dir, resid=late), f)
+    w0 = orc.weights(tau0, f)
+    assert np.max(np.abs(w[1] - w0[1])) < 1e-9
+    assert np.max(np.abs(w[0, :, 2] - w0[0, :, 2])) > 1e-3
+
+
+def test_residual_delay_in_the_weights_equals_the_per_sample_phase_correction():
+    """Folding the residual delay into the weights gives the beams of the
+    paper's per-sample complex multiplication followed by the geometric
+    weights: w(tau - delta) x = w(tau) (exp(+2 pi i f delta) x).  The two
+    sides run different code (the C weights and beam former against numpy's
+    phase product and einsum)."""
+    rng = np.random.default_rng([1105, 661, 103])
+    blk = synth.make_block(6, 4, 2, 8, 24, "ci16", 40.0, tag=(1105, 661, 103))
+    resid = rng.uniform(-2.5e-6, 2.5e-6, size=6)          # up to half a subband sample
+    w_geo = orc.block_weights(blk)
+    y_phase = _einsum_beams(w_geo, orc.phase_correct(blk.x, blk.freq_hz, resid))
+    w_res = orc.weights(orc.delays(blk.station_xyz, blk.beam_dir, blk.ref_dir, resid=resid), blk.freq_hz)
+    y_w = orc.beamform(blk.x, w_res)
+    assert np.max(np.abs(y_w - y_phase)) <= 1e-9 * np.max(np.abs(y_phase))
+    # the pipeline takes the same residual delays
+    v = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, 0, resid=resid)
+    assert np.max(np.abs(v - y_phase.transpose(1, 3, 2, 0))) <= 1e-9 * np.max(np.abs(y_phase))
+    # a zero residual changes nothing
+    assert np.array_equal(orc.phase_correct(blk.x, blk.freq_hz, np.zeros(6)), _cx(blk.x))
+
+
+def test_shift_and_residual_phase_make_fractionally_delayed_stations_coherent():
+    """Stations receive the same tones d_s + phi_s subband samples late (d_s
+    whole, |phi_s| <= 1/2).  Shifting each series by d_s (channeliser) and
+    removing the residual phi_s / 195312.5 s with the per-sample phase adds
+    every station coherently in every tone channel: |sum_s| = S nch A, up to
+    the rounding of the samples to integers (at most sqrt(2)/2 per sample, so
+    S nch sqrt(2)/2 after the FFT and the station sum).  Without the shift,
+    without the residual phase, with the opposite sign, or with the
+    baseband instead of the sky frequency, the stations do not add up."""
+    S, nsb, nch, T = 6, 2, 16, 256
+    rng = np.random.default_rng([1105, 661, 104])
+    d = rng.integers(0, 40, size=S)
+    d[0] = 0
+    phi = rng.uniform(-0.5, 0.5, size=S)
+    A = 6000.0
+    tones = [(0, 3, A, (0.4, 1.3)), (1, 11, A, (2.0, -0.7)), (1, 5, A, (0.1, 0.2))]
+    x = synth.delayed_subband_tones(S, nsb, nch, T + 48, d + phi, tones)
+    freq = synth.centred_channel_freqs(nsb, nch)
+    resid = phi / synth.SUBBAND_HZ
+    full = S * nch * A
+    bound = S * nch * math.sqrt(2) / 2
+    tone_ch = [sb * nch + q for sb, q, _, _ in tones]
+
+    ch = orc.channelize(x, nch, t_sb=T, shift=d)                      # [S][C][T/nch][2]
+    good = orc.phase_correct(ch, freq, resid).sum(axis=0)             # unit weights, zero geometric delay
+    for c in tone_ch:
+        assert np.all(np.abs(np.abs(good[c]) - full) <= bound), c
+    quiet = np.delete(good, tone_ch, axis=0)
+    assert np.abs(quiet).max() <= bound
+
+    def worst(summed):
+        return min(np.abs(summed[c]).min() for c in tone_ch) / full
+
+    assert worst(ch.sum(axis=0)) < 0.9                                              # no residual phase
+    assert worst(orc.phase_correct(ch, freq, -resid).sum(axis=0)) < 0.9            # opposite sign
+    f_mix = np.repeat((768 + np.arange(nsb)) * synth.SUBBAND_HZ, nch)
+    assert worst(orc.phase_correct(ch, freq - f_mix, resid).sum(axis=0)) < 0.9     # baseband frequency
+    plain = orc.channelize(x, nch, t_sb=T)
+    assert worst(orc.phase_correct(plain, freq, resid).sum(axis=0)) < 0.9          # no whole-sample shift
