@@ -61,26 +61,36 @@ const char* lbf_version(void);
 /*
  * Geometric delays and complex weights (Section 3; Section 4.3: each beam's
  * weights depend on the station location, the channel frequency and the beam
- * coordinates).
+ * coordinates), with the sub-sample part of delay compensation (Section 3:
+ * once the station series are shifted against each other by whole samples,
+ * e.g. by lbf_channelize, the delay that remains is removed by a phase
+ * rotation of each sample, which the weights carry):
  *
- *   tau[b][s] = p_s . (u_b - u_ref) / c0           (u_ref = 0 if ref_dir NULL)
+ *   tau[b][s] = p_s . (u_b - u_ref) / c0 - delta_s   (u_ref = 0 if ref_dir NULL,
+ *                                                     delta_s = 0 if d_station_delay NULL)
  *   w[c][b][s] = exp(-2 pi i (m - rint(m))),  m = f_c * tau[b][s]
  *
  * Computed in FP64 on the device, then rounded once (round-to-nearest-even)
  * to the weight type.
- *   d_station_xyz [S][3] f64, metres (local East-North-Up frame)
- *   d_beam_dir    [B][3] f64, unit direction vectors
- *   ref_dir       HOST [3] f64 or NULL
- *   d_freq_hz     [C]    f64
- *   d_w           [C][B][S] complex of wtype (complex f32: 8 bytes; complex
- *                 f16 / bf16: 4 bytes per weight)
- *   d_tau         [B][S] f64 seconds, or NULL
+ *   d_station_xyz   [S][3] f64, metres (local East-North-Up frame)
+ *   d_beam_dir      [B][3] f64, unit direction vectors
+ *   ref_dir         HOST [3] f64 or NULL
+ *   d_station_delay [S] f64 seconds or NULL: each station's residual delay
+ *                   (positive when its signal arrives late); the weight then
+ *                   advances that station's phase by 2 pi f_c delta_s.  Exact
+ *                   as the residual after a whole-sample shift when the
+ *                   subbands are centred on whole multiples of the subband
+ *                   sample rate, as a station's polyphase filter bank forms them
+ *   d_freq_hz       [C] f64, the channels' sky frequencies
+ *   d_w             [C][B][S] complex of wtype (complex f32: 8 bytes; complex
+ *                   f16 / bf16: 4 bytes per weight)
+ *   d_tau           [B][S] f64 seconds (including -delta_s), or NULL
  * Errors: LBF_E_INVAL for sizes < 1, NULL d_* inputs/outputs, unknown wtype,
  * B*S above 2^30 or C above 2097120.
  */
 int lbf_compute_weights(const double* d_station_xyz, int S, const double* d_beam_dir, int B,
-                        const double* ref_dir, const double* d_freq_hz, int C, int wtype,
-                        void* d_w, double* d_tau, void* stream);
+                        const double* ref_dir, const double* d_station_delay, const double* d_freq_hz, int C,
+                        int wtype, void* d_w, double* d_tau, void* stream);
 
 /*
  * One beam-forming block (Section 4.3): per channel, the weighted complex
@@ -263,10 +273,32 @@ int lbf_dedisperse(const void* d_y, int C, int B, int T, int n_fft, const void* 
  */
 int lbf_probe(int kind, int iters, const void* d_src, void* d_dst, uint64_t bytes, double* work, void* stream);
 
+/*
+ * Host-side check of the fast workers' memory addressing (no device access,
+ * not part of the beam former): walks every buffer access their kernels make
+ * for this block -- weight, sample and output descriptors and every 32-bit
+ * offset, with the kernels' own address arithmetic -- and returns LBF_OK when
+ * every descriptor lies inside its buffer, no offset wraps and every store the
+ * epilogue means to make lands inside its descriptor; otherwise LBF_E_INVAL
+ * with the first offending access in lbf_last_error().  channel_major: as
+ * lbf_beamform_channel_major, else as lbf_beamform, whose Stokes go through
+ * staging of staging_cap bytes in channel passes (0: the whole block at once).
+ * Blocks the fast workers do not take check as LBF_OK with no access.  The
+ * buffers are sized from the block; its pointers are not dereferenced (any
+ * non-NULL value).  threads: host threads for the walk (1..64).
+ * *accesses (may be NULL) receives the number of accesses walked.
+ */
+int lbf_check_addressing(const lbf_block* blk, int channel_major, uint64_t staging_cap, int threads,
+                         uint64_t* accesses);
+
 /* Bytes of each operand of a block (host arithmetic, no device access). */
 typedef struct {
     uint64_t input_bytes, weight_bytes, output_bytes;
     double flops;          /* 8 flops per complex multiply-add, both polarisations */
+    uint64_t staging_bytes;          /* Stokes staging lbf_beamform takes for the whole block
+                                        (the channel-major products before the reorder); 0 if none */
+    uint64_t staging_channel_bytes;  /* the same for one channel: the least staging a channel
+                                        pass needs                                            */
 } lbf_block_sizes;
 int lbf_block_footprint(const lbf_block* blk, lbf_block_sizes* out);
 
@@ -288,6 +320,10 @@ typedef struct {
     int queue_capacity;       /* host queue bound (>= 1); submit returns BUSY beyond */
     int max_batch;            /* jobs fused per launch (1..LBF_MAX_BATCH)            */
     int device;               /* HIP device ordinal                                  */
+    uint64_t staging_cap;     /* most arena bytes one job's Stokes staging takes (the
+                                 fast workers' channel-major products before the
+                                 reorder; a larger block runs in channel passes);
+                                 0: 256 MiB.  Counted in the job's footprint.       */
 } lbf_server_cfg;
 
 typedef struct {
@@ -295,6 +331,9 @@ typedef struct {
     const double* station_xyz; int S;   /* HOST [S][3] f64, copied at submit         */
     const double* beam_dir; int B;      /* HOST [B][3] f64, copied at submit         */
     const double* ref_dir;              /* HOST [3] f64 or NULL                      */
+    const double* station_delay;        /* HOST [S] f64 residual delays (s) or NULL,
+                                           copied at submit; part of the observation's
+                                           geometry (the weight-cache key)           */
     const double* freq_hz; int C;       /* HOST [C] f64, copied at submit            */
     const void* x; int xtype; int T;    /* station samples [S][C][T][2]              */
     int x_on_host;            /* 1: x is HOST memory, copied into the arena;
@@ -338,8 +377,9 @@ typedef struct {
 int lbf_server_create(const lbf_server_cfg* cfg, lbf_server** out);
 
 /* Non-blocking.  LBF_E_INVAL for a malformed job (or a stream block whose S, C,
- * xtype or t_int differ from its stream's), LBF_E_NOMEM if its footprint can
- * never fit the arena, LBF_E_BUSY if the host queue is full, LBF_E_HIP for a
+ * xtype or t_int differ from its stream's), LBF_E_NOMEM if its footprint
+ * (weights, host-sample staging, stream carry, Stokes staging) can never fit
+ * the arena or one channel's Stokes staging exceeds staging_cap, LBF_E_BUSY if the host queue is full, LBF_E_HIP for a
  * block of a stream an earlier block of which failed. */
 int lbf_server_submit(lbf_server* srv, const lbf_job* job, uint64_t* ticket);
 

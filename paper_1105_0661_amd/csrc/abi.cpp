@@ -7,8 +7,10 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/lbf.h"
+#include "lbf_internal.h"
 #include "lbf_launch.h"
 
 static_assert(LBF_MAX_BATCH == lbf::kMaxBatch, "batch bound mismatch");
@@ -80,6 +82,8 @@ lbf::BlockDesc to_desc(const lbf_block* b) {
     d.b0 = 0;
     d.b1 = b->B;
     d.ld_row = b->B * (b->product == LBF_STOKES_IQUV ? 4 : 1);
+    d.c0 = 0;
+    d.nc = b->C;
     return d;
 }
 
@@ -106,6 +110,51 @@ int counter_slot(int** out) {
 
 }  // namespace
 
+size_t lbf::block_staging_channel_bytes(const lbf_block* b) {
+    const lbf::BlockDesc d = to_desc(b);
+    return lbf::needs_staging(d) ? lbf::staging_channel_bytes(d) : 0;
+}
+
+int lbf::run_block(const lbf_block* blk, void* stage, size_t cap, void* stream, const char* where) {
+    int rc = check_block(blk, where);
+    if (rc) return rc;
+    const lbf::BlockDesc d = to_desc(blk);
+    if (stage != nullptr && lbf::needs_staging(d) && lbf::staging_chunk(d, cap) < 1)
+        return fail(LBF_E_NOMEM, "%s: staging of %zu bytes holds less than one channel (%zu bytes)", where, cap,
+                    lbf::staging_channel_bytes(d));
+    hipError_t e = stage ? lbf::launch_beamform_staged(d, stage, cap, (hipStream_t)stream)
+                         : lbf::launch_beamform(d, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, where);
+    return ok();
+}
+
+int lbf::run_batch(const lbf_block* blks, int n, void* const* stage, const size_t* cap, void* stream,
+                   const char* where) {
+    if (!blks) return fail(LBF_E_INVAL, "%s: blocks is NULL", where);
+    if (n < 1 || n > LBF_MAX_BATCH) return fail(LBF_E_INVAL, "%s: n=%d outside 1..%d", where, n, LBF_MAX_BATCH);
+    lbf::BlockDesc d[lbf::kMaxBatch];
+    for (int i = 0; i < n; ++i) {
+        int rc = check_block(&blks[i], where);
+        if (rc) return rc;
+        if (blks[i].product == LBF_VOLTAGES)
+            return fail(LBF_E_UNSUPPORTED, "%s: block %d: batches take Stokes products", where, i);
+        if (blks[i].ctype == LBF_F32)
+            return fail(LBF_E_UNSUPPORTED, "%s: block %d: batches take F16 or BF16 operands", where, i);
+        if (blks[i].ctype != blks[0].ctype)
+            return fail(LBF_E_UNSUPPORTED, "%s: all blocks of a batch share one ctype", where);
+        d[i] = to_desc(&blks[i]);
+        if (stage != nullptr && lbf::needs_staging(d[i]) &&
+            (stage[i] == nullptr || lbf::staging_chunk(d[i], cap[i]) < 1))
+            return fail(LBF_E_NOMEM, "%s: block %d: staging holds less than one channel", where, i);
+    }
+    int* counter = nullptr;
+    int rc = counter_slot(&counter);
+    if (rc) return rc;
+    hipError_t e = lbf::launch_beamform_batch(d, n, counter, stage, cap, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, where);
+    return ok();
+}
+
 int lbf::set_error(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -123,7 +172,8 @@ const char* lbf_last_error(void) { return g_err.c_str(); }
 const char* lbf_version(void) { return "lbf 1.0 gfx950"; }
 
 int lbf_compute_weights(const double* d_station_xyz, int S, const double* d_beam_dir, int B, const double* ref_dir,
-                        const double* d_freq_hz, int C, int wtype, void* d_w, double* d_tau, void* stream) {
+                        const double* d_station_delay, const double* d_freq_hz, int C, int wtype, void* d_w,
+                        double* d_tau, void* stream) {
     if (S < 1 || B < 1 || C < 1)
         return fail(LBF_E_INVAL, "lbf_compute_weights: sizes must be >= 1 (S=%d B=%d C=%d)", S, B, C);
     if (!d_station_xyz || !d_beam_dir || !d_freq_hz || !d_w)
@@ -132,18 +182,14 @@ int lbf_compute_weights(const double* d_station_xyz, int S, const double* d_beam
     if ((long long)B * S > (1LL << 30) || C > 65535 * 32)
         return fail(LBF_E_INVAL, "lbf_compute_weights: too large (B*S=%lld, C=%d)", (long long)B * S, C);
     const double rx = ref_dir ? ref_dir[0] : 0.0, ry = ref_dir ? ref_dir[1] : 0.0, rz = ref_dir ? ref_dir[2] : 0.0;
-    hipError_t e = lbf::launch_weights(d_station_xyz, S, d_beam_dir, B, rx, ry, rz, d_freq_hz, C, wtype, d_w, d_tau,
-                                       (hipStream_t)stream);
+    hipError_t e = lbf::launch_weights(d_station_xyz, S, d_beam_dir, B, rx, ry, rz, d_station_delay, d_freq_hz, C,
+                                       wtype, d_w, d_tau, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lbf_compute_weights");
     return ok();
 }
 
 int lbf_beamform(const lbf_block* blk, void* stream) {
-    int rc = check_block(blk, "lbf_beamform");
-    if (rc) return rc;
-    hipError_t e = lbf::launch_beamform(to_desc(blk), (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "lbf_beamform");
-    return ok();
+    return lbf::run_block(blk, nullptr, 0, stream, "lbf_beamform");
 }
 
 int lbf_beamform_channel_major(const lbf_block* blk, void* stream) {
@@ -166,32 +212,13 @@ int lbf_beam_major(const float* d_in, int C2, int K, int T2, int B, float* d_out
     if (a < b + bytes && b < a + bytes) return fail(LBF_E_INVAL, "lbf_beam_major: input and output overlap");
     if ((long long)K * T2 > 0x7fffffffLL || C2 > (1 << 26) || B > (1 << 26))
         return fail(LBF_E_INVAL, "lbf_beam_major: too large");
-    hipError_t e = lbf::launch_stage_to_beam_major(d_in, C2, T2, B * K, B * K, d_out, (hipStream_t)stream);
+    hipError_t e = lbf::launch_stage_to_beam_major(d_in, C2, T2, B * K, B * K, d_out, (size_t)C2, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lbf_beam_major");
     return ok();
 }
 
 int lbf_beamform_batch(const lbf_block* blks, int n, void* stream) {
-    if (!blks) return fail(LBF_E_INVAL, "lbf_beamform_batch: blocks is NULL");
-    if (n < 1 || n > LBF_MAX_BATCH) return fail(LBF_E_INVAL, "lbf_beamform_batch: n=%d outside 1..%d", n, LBF_MAX_BATCH);
-    lbf::BlockDesc d[lbf::kMaxBatch];
-    for (int i = 0; i < n; ++i) {
-        int rc = check_block(&blks[i], "lbf_beamform_batch");
-        if (rc) return rc;
-        if (blks[i].product == LBF_VOLTAGES)
-            return fail(LBF_E_UNSUPPORTED, "lbf_beamform_batch: block %d: batches take Stokes products", i);
-        if (blks[i].ctype == LBF_F32)
-            return fail(LBF_E_UNSUPPORTED, "lbf_beamform_batch: block %d: batches take F16 or BF16 operands", i);
-        if (blks[i].ctype != blks[0].ctype)
-            return fail(LBF_E_UNSUPPORTED, "lbf_beamform_batch: all blocks of a batch share one ctype");
-        d[i] = to_desc(&blks[i]);
-    }
-    int* counter = nullptr;
-    int rc = counter_slot(&counter);
-    if (rc) return rc;
-    hipError_t e = lbf::launch_beamform_batch(d, n, counter, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "lbf_beamform_batch");
-    return ok();
+    return lbf::run_batch(blks, n, nullptr, nullptr, stream, "lbf_beamform_batch");
 }
 
 int lbf_stokes(const float* d_y, int B, int C, int T, int product, int t_int, int f_int, float* d_s, void* stream) {
@@ -329,6 +356,19 @@ int lbf_probe(int kind, int iters, const void* d_src, void* d_dst, uint64_t byte
     return LBF_OK;
 }
 
+int lbf_check_addressing(const lbf_block* blk, int channel_major, uint64_t staging_cap, int threads,
+                         uint64_t* accesses) {
+    int rc = check_block(blk, "lbf_check_addressing");
+    if (rc) return rc;
+    if (threads < 1 || threads > 64) return fail(LBF_E_INVAL, "lbf_check_addressing: threads must be 1..64");
+    char msg[400];
+    const int r = lbf::check_block_addressing(to_desc(blk), channel_major != 0, (size_t)staging_cap, threads, accesses,
+                                              msg, sizeof(msg));
+    if (r == 2) return fail(LBF_E_NOMEM, "lbf_check_addressing: staging holds less than one channel");
+    if (r != 0) return fail(LBF_E_INVAL, "lbf_check_addressing: %s", msg);
+    return ok();
+}
+
 int lbf_block_footprint(const lbf_block* b, lbf_block_sizes* out) {
     if (!out) return fail(LBF_E_INVAL, "lbf_block_footprint: out is NULL");
     if (!b) return fail(LBF_E_INVAL, "lbf_block_footprint: block is NULL");
@@ -344,6 +384,14 @@ int lbf_block_footprint(const lbf_block* b, lbf_block_sizes* out) {
     if (b->product == LBF_VOLTAGES) out->output_bytes = C * B * T * 2 * 8;
     else out->output_bytes = B * (uint64_t)b->product * (T / b->t_int) * (C / b->f_int) * 4;
     out->flops = 8.0 * (double)B * (double)S * (double)C * (double)T * 2.0;
+    out->staging_channel_bytes = 0;
+    out->staging_bytes = 0;
+    if (b->product != LBF_VOLTAGES && b->T % b->t_int == 0 && b->C % b->f_int == 0) {
+        lbf_block v = *b;
+        v.d_x = v.d_w = v.d_out = (void*)b;   // sizes only: any non-NULL pointer
+        out->staging_channel_bytes = lbf::block_staging_channel_bytes(&v);
+        out->staging_bytes = out->staging_channel_bytes * C;
+    }
     return ok();
 }
 

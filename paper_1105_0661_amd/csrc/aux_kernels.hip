@@ -7,8 +7,9 @@ namespace lbf {
 
 // ---------------------------------------------------------------------------
 // Weights (Section 3 and Section 4.3 of Mol & Romein): the delay of station s
-// for beam b, tau = p_s . (u_b - u_ref) / c0, and the phase-shift weight
-// w = exp(-2 pi i frac(f tau)).  Everything up to the final rounding is FP64:
+// for beam b, tau = p_s . (u_b - u_ref) / c0 - delta_s (delta_s: the station's
+// residual delay after a whole-sample shift, Section 3), and the phase-shift
+// weight w = exp(-2 pi i frac(f tau)).  Everything up to the final rounding is FP64:
 // f * tau spans many turns and only its fractional part matters.
 // One thread per (b, s) and group of kWChan channels: tau once, then one
 // weight per channel; threads of a block are consecutive (b, s), so each
@@ -76,14 +77,14 @@ __device__ inline void weight_of_turn(double r, const CisCoef& k, double* wr, do
 template <int WT>
 __global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__ pos, int S,
                                                       const double* __restrict__ dir, int B, double rx, double ry,
-                                                      double rz, const double* __restrict__ freq, int C, void* w,
-                                                      double* tau) {
+                                                      double rz, const double* __restrict__ delay,
+                                                      const double* __restrict__ freq, int C, void* w, double* tau) {
     const int bs = blockIdx.x * blockDim.x + threadIdx.x;
     if (bs >= B * S) return;
     const int b = bs / S, s = bs - b * S;
     const double dx = dir[3 * b + 0] - rx, dy = dir[3 * b + 1] - ry, dz = dir[3 * b + 2] - rz;
     const double proj = pos[3 * s + 0] * dx + pos[3 * s + 1] * dy + pos[3 * s + 2] * dz;
-    const double t = proj / kC0;
+    const double t = proj / kC0 - (delay != nullptr ? delay[s] : 0.0);
     if (tau != nullptr && blockIdx.y == 0) tau[bs] = t;
     const int c0 = blockIdx.y * kWChan, c1 = min(C, c0 + kWChan);
     const size_t BS = (size_t)B * S;
@@ -113,12 +114,16 @@ __global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__
 }
 
 hipError_t launch_weights(const double* pos, int S, const double* dir, int B, double rx, double ry, double rz,
-                          const double* freq, int C, int wtype, void* w, double* tau, hipStream_t st) {
+                          const double* delay, const double* freq, int C, int wtype, void* w, double* tau,
+                          hipStream_t st) {
     const int bs = B * S;
     dim3 g((unsigned)((bs + 255) / 256), (unsigned)((C + kWChan - 1) / kWChan)), b(256);
-    if (wtype == CT_F32) hipLaunchKernelGGL(weights_kernel<CT_F32>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, freq, C, w, tau);
-    else if (wtype == CT_F16) hipLaunchKernelGGL(weights_kernel<CT_F16>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, freq, C, w, tau);
-    else hipLaunchKernelGGL(weights_kernel<CT_BF16>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, freq, C, w, tau);
+    if (wtype == CT_F32)
+        hipLaunchKernelGGL(weights_kernel<CT_F32>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, delay, freq, C, w, tau);
+    else if (wtype == CT_F16)
+        hipLaunchKernelGGL(weights_kernel<CT_F16>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, delay, freq, C, w, tau);
+    else
+        hipLaunchKernelGGL(weights_kernel<CT_BF16>, g, b, 0, st, pos, S, dir, B, rx, ry, rz, delay, freq, C, w, tau);
     return hipGetLastError();
 }
 
@@ -289,7 +294,8 @@ hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int el
 
 // ---------------------------------------------------------------------------
 // Channel-major staging s[c][m][b] (rows of ldb >= B values) -> out[b][m][c]
-// (Section 4.6).  For Stokes the staging is [c][t'][beam][k]: m = t' and the
+// (Section 4.6), output rows of ldo >= C2 channels (a chunk of the channels
+// goes to columns [0, C2) of rows that hold all of them).  For Stokes the staging is [c][t'][beam][k]: m = t' and the
 // B index runs over (beam, k) pairs, so out[(beam k)][t'][c] is the final
 // [beam][k][t'][c].  Each work group moves a
 // 64-channel x 64-beam tile of one m through LDS: reads are 256-byte runs
@@ -302,7 +308,8 @@ hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int el
 // ---------------------------------------------------------------------------
 template <bool VEC>
 __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* __restrict__ in, int C2, int M, int B,
-                                                                  int ldb, float* __restrict__ out, int walk) {
+                                                                  int ldb, float* __restrict__ out, size_t ldo,
+                                                                  int walk) {
     __shared__ float tile[64][65];
     int bt, ct;
     size_t m;
@@ -333,7 +340,7 @@ __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* _
     for (int p = 0; p < 4; ++p) {
         const int rb = p * 16 + rr, b = b0 + rb, c = c0 + 4 * q;
         if (b >= B) continue;
-        float* dst = out + ((size_t)b * M + m) * C2 + c;
+        float* dst = out + ((size_t)b * M + m) * ldo + c;
         if (VEC && c + 3 < C2) {
             float4 v;
             v.x = tile[4 * q + 0][rb];
@@ -349,15 +356,16 @@ __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* _
     }
 }
 
-hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, int ldb, float* out, hipStream_t st) {
+hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, int ldb, float* out, size_t ldo,
+                                      hipStream_t st) {
     const unsigned nm = (unsigned)M, nc = (unsigned)((C2 + 63) / 64), nb = (unsigned)((B + 63) / 64);
     const int walk = M > 65535 || nc > 65535 ? 0 : ldb % 32 == 0 ? 1 : 2;
     const dim3 g = walk == 0 ? dim3(nm, nc, nb) : walk == 1 ? dim3(nc, nm, nb) : dim3(nb, nc, nm), b(256);
     const bool aligned = ((reinterpret_cast<uintptr_t>(stage) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
-    if (aligned && ldb % 4 == 0 && C2 % 4 == 0)
-        hipLaunchKernelGGL(stage_to_beam_major_kernel<true>, g, b, 0, st, stage, C2, M, B, ldb, out, walk);
+    if (aligned && ldb % 4 == 0 && C2 % 4 == 0 && ldo % 4 == 0)
+        hipLaunchKernelGGL(stage_to_beam_major_kernel<true>, g, b, 0, st, stage, C2, M, B, ldb, out, ldo, walk);
     else
-        hipLaunchKernelGGL(stage_to_beam_major_kernel<false>, g, b, 0, st, stage, C2, M, B, ldb, out, walk);
+        hipLaunchKernelGGL(stage_to_beam_major_kernel<false>, g, b, 0, st, stage, C2, M, B, ldb, out, ldo, walk);
     return hipGetLastError();
 }
 

@@ -102,43 +102,28 @@ hipError_t launch_batch_variant(int v, const BatchArgs& a, int* counter, hipStre
     }
 }
 
-hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, hipStream_t st) {
-    // blocks outside the batch kernel's path: their own launches
+// One group of batch-kernel blocks; block idx[g] forms its Stokes products
+// channel-major in stage[g], then they are reordered into its final order.
+static hipError_t run_batch_group(const BlockDesc* blks, const int* idx, int n, char* const* stage, int* d_counter,
+                                  hipStream_t st) {
     BatchArgs a;
     a.n = 0;
     a.item_start[0] = 0;
-    size_t stage_bytes = 0, stage_off[kMaxBatch];
-    int src[kMaxBatch], nsrc = 0, entry_src[kMaxBatch];
-    for (int j = 0; j < n; ++j) {
-        if (!batch_fast(blks[j])) {
-            const hipError_t e = launch_beamform(blks[j], st);
-            if (e != hipSuccess) return e;
-            continue;
-        }
-        const int K = blks[j].product == PR_IQUV ? 4 : 1;
-        stage_off[nsrc] = stage_bytes;
-        stage_bytes += ((size_t)blks[j].C * (blks[j].T / blks[j].t_int) * staging_ld(blks[j].B, K) * sizeof(float) +
-                        255) & ~(size_t)255;
-        src[nsrc] = j;
+    int entry_src[kMaxBatch];
+    for (int g = 0; g < n; ++g) {
+        const BlockDesc& b = blks[idx[g]];
         // a beam tail of at most 128 beams becomes an entry of its own while
         // the argument block has room (it holds kMaxBatch entries)
         BlockDesc part[2];
-        int np = split_fast_h(blks[j], part);
-        if (a.n + np + (n - 1 - j) > kMaxBatch) np = 1, part[0] = blks[j];
+        int np = split_fast_h(b, part);
+        if (a.n + np + (n - 1 - g) > kMaxBatch) np = 1, part[0] = b;
         for (int p = 0; p < np; ++p) {
-            entry_src[a.n] = nsrc;
+            entry_src[a.n] = g;
             a.blk[a.n++] = part[p];
         }
-        nsrc++;
     }
-    if (a.n == 0) return hipSuccess;
-    // Stokes go to channel-major staging first (as in lbf_beamform), then to
-    // the beam-major outputs
-    char* stage = nullptr;
-    hipError_t e = staging_alloc((void**)&stage, stage_bytes, st);
-    if (e != hipSuccess) return e;
     for (int j = 0; j < a.n; ++j) {
-        a.blk[j].out = stage + stage_off[entry_src[j]];
+        a.blk[j].out = stage[entry_src[j]];
         a.blk[j].order = 1;
         a.blk[j].ld_row = staging_ld(a.blk[j].B, a.blk[j].product == PR_IQUV ? 4 : 1);
         int nbg;
@@ -148,6 +133,7 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
     }
     // one launch per variant present, in variant order, on the same stream;
     // the counter is reset before each
+    hipError_t e = hipSuccess;
     for (int v = 0; v < kBatchVariants && e == hipSuccess; ++v) {
         BatchArgs g;
         g.n = 0;
@@ -163,13 +149,50 @@ hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, h
         e = a.blk[0].ctype == CT_F16 ? launch_batch_variant<CT_F16>(v, g, d_counter, st)
                                      : launch_batch_variant<CT_BF16>(v, g, d_counter, st);
     }
-    for (int j = 0; j < nsrc && e == hipSuccess; ++j) {
-        const BlockDesc& b = blks[src[j]];
+    for (int g = 0; g < n && e == hipSuccess; ++g) {
+        const BlockDesc& b = blks[idx[g]];
         const int K = b.product == PR_IQUV ? 4 : 1;
-        e = launch_stage_to_beam_major((const float*)(stage + stage_off[j]), b.C, b.T / b.t_int, b.B * K,
-                                       staging_ld(b.B, K), (float*)b.out, st);
+        e = launch_stage_to_beam_major((const float*)stage[g], b.C, b.T / b.t_int, b.B * K, staging_ld(b.B, K),
+                                       (float*)b.out, (size_t)b.C, st);
     }
-    const hipError_t ef = hipFreeAsync(stage, st);
+    return e;
+}
+
+static size_t staging_block_bytes(const BlockDesc& b) {
+    return ((size_t)b.C * staging_channel_bytes(b) + 255) & ~(size_t)255;
+}
+
+hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, void* const* stage, const size_t* cap,
+                                 hipStream_t st) {
+    int idx[kMaxBatch], nb = 0;
+    char* sp[kMaxBatch];
+    size_t total = 0;
+    for (int j = 0; j < n; ++j) {
+        const bool fits = stage == nullptr || (stage[j] != nullptr && staging_block_bytes(blks[j]) <= cap[j]);
+        if (batch_fast(blks[j]) && fits) {
+            sp[nb] = stage ? (char*)stage[j] : nullptr;
+            idx[nb++] = j;
+            total += staging_block_bytes(blks[j]);
+            continue;
+        }
+        // outside the batch kernel's path, or staging that holds only part of
+        // the block's channels: its own launches
+        const hipError_t e = stage ? launch_beamform_staged(blks[j], stage[j], cap[j], st) : launch_beamform(blks[j], st);
+        if (e != hipSuccess) return e;
+    }
+    if (nb == 0) return hipSuccess;
+    if (stage != nullptr) return run_batch_group(blks, idx, nb, sp, d_counter, st);
+    // staging of the whole batch from the stream-ordered pool
+    char* pool = nullptr;
+    hipError_t e = staging_alloc((void**)&pool, total, st);
+    if (e != hipSuccess) return e;
+    size_t o = 0;
+    for (int g = 0; g < nb; ++g) {
+        sp[g] = pool + o;
+        o += staging_block_bytes(blks[idx[g]]);
+    }
+    e = run_batch_group(blks, idx, nb, sp, d_counter, st);
+    const hipError_t ef = hipFreeAsync(pool, st);
     return e != hipSuccess ? e : ef;
 }
 

@@ -11,6 +11,7 @@
 // (sample, beam): the Stokes epilogue (Section 4.5) and the integration over
 // up to 16 samples (Section 5.1) need no data exchange between lanes.
 #pragma once
+#include "bf_addr.h"
 #include "lbf_device.h"
 #include "lbf_launch.h"
 
@@ -278,55 +279,15 @@ LBF_INLINE void stage_weights_h(uint32_t* wh, const BlockDesc& d, int c, int b0,
     }
 }
 
-// Fast-path staging (S <= 64): every thread issues all of its loads before
-// the first LDS write, so one item's weights cost about one memory latency.
-// Buffer loads over the channel's [B][S] block read beams >= B as zero;
-// stations >= S are zeroed explicitly.
+// Weight descriptor of channel c: the channel's [B][S] block; beams >= B and
+// stations past the block read as zero.
 LBF_INLINE __amdgpu_buffer_rsrc_t weight_rsrc(const BlockDesc& d, int c, int bytes) {
-    const uint64_t base = reinterpret_cast<uint64_t>(d.w) + (uint64_t)c * d.B * d.S * bytes;
+    const uint64_t base = reinterpret_cast<uint64_t>(d.w) + weight_base(d, c, bytes);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-    const uint32_t nrec = __builtin_amdgcn_readfirstlane((uint32_t)d.B * (uint32_t)d.S * (uint32_t)bytes);
+    const uint32_t nrec = __builtin_amdgcn_readfirstlane(weight_range(d, bytes));
     return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0, (int)nrec,
                                              0x00020000);
-}
-
-// wh[b][s] packed 16-bit complex: wave w fills rows w, w+4, ..., lane = station
-LBF_INLINE void stage_weights_h_fast(uint32_t* wh, const BlockDesc& d, int c, int b0) {
-    constexpr int R = kBeamGroup / kWavesPerGroup;   // rows per wave
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const __amdgpu_buffer_rsrc_t rs = weight_rsrc(d, c, 4);
-    const bool sok = lane < d.S;
-    uint32_t v[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int b = b0 + wave + kWavesPerGroup * k;
-        v[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(((uint32_t)b * d.S + lane) * 4u), 0, 0);
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k) wh[(wave + kWavesPerGroup * k) * kWRow + lane] = sok ? v[k] : 0u;
-}
-
-// wl[s][ri][b] floats: thread -> beam (bl = tid % 128), stations 2k + tid/128
-LBF_INLINE void stage_weights_f32_fast(float* wl, const BlockDesc& d, int c, int b0) {
-    constexpr int R = kStationChunk * kBeamGroup / kThreads;   // 32 per thread
-    typedef float float2v __attribute__((ext_vector_type(2)));
-    const int bl = threadIdx.x % kBeamGroup, s1 = threadIdx.x / kBeamGroup;
-    const __amdgpu_buffer_rsrc_t rs = weight_rsrc(d, c, 8);
-    const uint32_t rowoff = (uint32_t)(b0 + bl) * (uint32_t)d.S;
-    float2v v[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int sl = 2 * k + s1;
-        v[k] = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)((rowoff + sl) * 8u), 0, 0);
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int sl = 2 * k + s1;
-        const bool ok = sl < d.S;
-        wl[(sl * 2 + 0) * kBeamGroup + bl] = ok ? v[k][0] : 0.f;
-        wl[(sl * 2 + 1) * kBeamGroup + bl] = ok ? v[k][1] : 0.f;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -469,14 +430,12 @@ LBF_INLINE void epilogue_tile(const floatx16 (&acc)[4], const EpiCtx& e, int bea
     }
 }
 
-// Branch-free stores of the fast FP16/BF16 worker.  rs covers one channel of
-// the output; a lane with nothing to store (beam >= B, sample past the end,
-// no tile) uses an offset past the end of the buffer, which the hardware
-// drops, so the epilogue has no control flow and interleaves freely with the
-// MFMAs of the next tile.  The offset is 2^31, not 2^32 - 1: the range check
-// adds the access size to the offset, and the latter would wrap around to an
-// in-range value.  Buffers are below 2^31 bytes (checked by the launcher).
-constexpr uint32_t kNoStore = 0x80000000u;
+// Branch-free stores of the fast workers.  The descriptor covers one channel
+// of the output; a lane with nothing to store (beam >= B, sample past the
+// end, no tile) uses the offset kNoStore, past the end of every output
+// descriptor, which the hardware drops, so the epilogue has no control flow
+// and interleaves freely with the MFMAs of the next tile.  Per-channel outputs
+// are below 2^31 bytes (fast_path).
 
 // off if ok, else kNoStore, as a lane select the compiler keeps (a plain ?:
 // is turned into a branch around the store)
@@ -487,8 +446,9 @@ LBF_INLINE uint32_t store_off(bool ok, uint32_t off) {
     return r;
 }
 
-LBF_INLINE __amdgpu_buffer_rsrc_t channel_rsrc(void* out, int c, uint32_t bytes_per_channel) {
-    const uint64_t base = reinterpret_cast<uint64_t>(out) + (uint64_t)c * bytes_per_channel;
+// output descriptor of channel c of the item's block (index c - c0)
+LBF_INLINE __amdgpu_buffer_rsrc_t channel_rsrc(const BlockDesc& d, int c, uint32_t bytes_per_channel) {
+    const uint64_t base = reinterpret_cast<uint64_t>(d.out) + out_base(d, c, bytes_per_channel);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
     return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0,
@@ -500,7 +460,7 @@ LBF_INLINE __amdgpu_buffer_rsrc_t channel_rsrc(void* out, int c, uint32_t bytes_
 template <int PR>
 LBF_INLINE void stokes_store_row(const float (&v)[4], __amdgpu_buffer_rsrc_t rs, int ld, int tq, int beam, bool ok) {
     if (PR == PR_IQUV) {
-        const uint32_t off = store_off(ok, ((uint32_t)tq * (uint32_t)ld + (uint32_t)beam * 4u) * 4u);
+        const uint32_t off = store_off(ok, stokes_off(tq, ld, beam, 4));
         floatx4 w;
         w[0] = v[0];
         w[1] = v[1];
@@ -508,7 +468,7 @@ LBF_INLINE void stokes_store_row(const float (&v)[4], __amdgpu_buffer_rsrc_t rs,
         w[3] = v[3];
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, w), rs, (int)off, 0, 0);
     } else {
-        const uint32_t off = store_off(ok, ((uint32_t)tq * (uint32_t)ld + (uint32_t)beam) * 4u);
+        const uint32_t off = store_off(ok, stokes_off(tq, ld, beam, 1));
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), rs, (int)off, 0, 0);
     }
 }
@@ -535,7 +495,7 @@ LBF_INLINE void volt_store_cm(const floatx16 (&acc)[4], __amdgpu_buffer_rsrc_t r
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int t = t0 + 16 * h + k;
-        const uint32_t off = store_off(ok && t < T, ((uint32_t)beam * T + t) * 16u);
+        const uint32_t off = store_off(ok && t < T, volt_off(beam, T, t));
         floatx4 v;
         v[0] = acc[0][k];
         v[1] = acc[1][k];
@@ -657,22 +617,23 @@ inline int split_fast_h(const BlockDesc& d, BlockDesc* part) {
     return 2;
 }
 
-// Work items of the fast FP16/BF16 worker: (channel, group of 256/NS beams,
-// segment of up to kSegTiles 32-sample tiles) -- long blocks are cut in time
-// so that few-channel blocks still spread over all compute units.
-constexpr int kSegTiles = 24;
+// Work items of the fast FP16/BF16 worker: (channel of [c0, c0 + nc), group
+// of 256/NS beams, segment of up to kSegTiles 32-sample tiles) -- long blocks
+// are cut in time so that few-channel blocks still spread over all compute
+// units.
 inline int block_items_fast_h(const BlockDesc& d, int* nbg) {
     const int per = 8 / fast_h_streams(d) * kTile;
     *nbg = (d.b1 - d.b0 + per - 1) / per;
     const int ntiles = (d.T + kTile - 1) / kTile;
-    return d.C * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
+    return d.nc * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
 }
 
-// work items of the fast FP32 worker: (channel, group of 128 beams, segment)
+// work items of the fast FP32 worker: (channel of [c0, c0 + nc), group of 128
+// beams, segment)
 inline int block_items_fast_f32(const BlockDesc& d, int* nbg) {
     *nbg = (d.B + kBeamGroup - 1) / kBeamGroup;
     const int ntiles = (d.T + kTile - 1) / kTile;
-    return d.C * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
+    return d.nc * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
 }
 
 // number of (channel group, beam group) work items of a block
@@ -703,20 +664,16 @@ __host__ __device__ inline bool fast_path(const BlockDesc& d) {
     return 8.0 * (double)d.C * (double)d.T * sample_bytes(d.xtype) < 2147483648.0 - 4096.0;
 }
 
-// Buffer resource over the samples of stations [s0, s0+8) of channel c
-// (x[s][c][t] with stride C*T between stations).  Offsets beyond the valid
-// stations (s >= S) are out of range and read as zero; the base address of a
-// fully invalid group is never dereferenced.
-LBF_INLINE __amdgpu_buffer_rsrc_t station_group_rsrc(const void* x, int bytes, int s0, int S, int c, int T,
-                                                     uint32_t stride_bytes) {
-    const uint64_t base = reinterpret_cast<uint64_t>(x) + (uint64_t)s0 * stride_bytes + (uint64_t)c * T * bytes;
-    int nvalid = S - s0;
-    nvalid = nvalid < 0 ? 0 : (nvalid > 8 ? 8 : nvalid);
+// Descriptor over the planes of the valid stations of group [s0, s0 + 8)
+// (group_base, group_range): offsets of stations >= S are out of range and
+// read as zero; a group with no valid station has range 0.
+LBF_INLINE __amdgpu_buffer_rsrc_t group_rsrc(const void* x, int s0, int S, uint32_t stride_bytes) {
+    const uint64_t base = reinterpret_cast<uint64_t>(x) + group_base(s0, stride_bytes);
     // the values are wave-uniform; keep them in scalar registers so the
     // buffer instruction takes them directly
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-    const uint32_t nrec = __builtin_amdgcn_readfirstlane((uint32_t)nvalid * stride_bytes);
+    const uint32_t nrec = __builtin_amdgcn_readfirstlane(group_range(s0, S, stride_bytes));
     return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0, (int)nrec,
                                              0x00020000);
 }

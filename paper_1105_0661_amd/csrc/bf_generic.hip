@@ -87,27 +87,70 @@ hipError_t staging_alloc(void** p, size_t bytes, hipStream_t st) {
     return hipMallocAsync(p, bytes, st);
 }
 
-// lbf_beamform: the fast workers where they apply, the generic ones otherwise.
 // The fast workers write Stokes products channel-major ([C'][T'][B][K], one
 // 16-byte store per beam and period for IQUV); a beam-major block (order 0)
 // goes through a staging buffer of that layout, rows padded to a multiple of
-// 32 floats (stream-ordered allocation), and a tiled transpose.
-hipError_t launch_beamform(const BlockDesc& d, hipStream_t st) {
+// 32 floats, and a tiled transpose.
+bool needs_staging(const BlockDesc& d) { return fast_path(d) && d.product != PR_VOLT && d.order == 0; }
+
+size_t staging_channel_bytes(const BlockDesc& d) {
+    const int K = d.product == PR_IQUV ? 4 : 1;
+    return (size_t)(d.T / d.t_int) * staging_ld(d.B, K) * sizeof(float);
+}
+
+// Channels per pass through a staging buffer of `cap` bytes: all of them if
+// they fit, else the most that fit rounded down to a multiple of 64 (or 4), so
+// that the reorder keeps its 16-byte stores; 0 if not even one channel fits.
+int staging_chunk(const BlockDesc& d, size_t cap) {
+    const size_t n = cap / staging_channel_bytes(d);
+    if (n >= (size_t)d.C) return d.C;
+    if (n >= 64) return (int)(n / 64 * 64);
+    if (n >= 4) return (int)(n / 4 * 4);
+    return (int)n;
+}
+
+hipError_t launch_beamform_direct(const BlockDesc& d, hipStream_t st) {
     if (!fast_path(d)) return launch_beamform_generic(d, st);
-    if (d.product == PR_VOLT || d.order == 1) return launch_fast(d, st);
+    return launch_fast(d, st);
+}
+
+// A block through caller-provided staging of `cap` bytes: the channels in
+// passes of staging_chunk(d, cap), each pass the contraction into the staging
+// buffer and the reorder of its channels into the final order; the passes are
+// ordered by the stream, so they reuse the buffer.
+hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, hipStream_t st) {
+    if (!needs_staging(d)) return launch_beamform_direct(d, st);
     const int K = d.product == PR_IQUV ? 4 : 1;
     const int T2 = d.T / d.t_int;
-    void* stage = nullptr;
     const int ld = staging_ld(d.B, K);
-    hipError_t e = staging_alloc(&stage, (size_t)d.C * T2 * ld * sizeof(float), st);
+    const int nc = staging_chunk(d, cap);
+    if (nc < 1 || stage == nullptr) return hipErrorInvalidValue;
+    for (int c0 = 0; c0 < d.C; c0 += nc) {
+        BlockDesc ds = d;
+        ds.out = stage;
+        ds.order = 1;
+        ds.ld_row = ld;
+        ds.c0 = c0;
+        ds.nc = d.C - c0 < nc ? d.C - c0 : nc;
+        hipError_t e = launch_fast(ds, st);
+        // [c][t'][b k] -> [b k][t'][c]: the beam-major final order [b][k][t'][c]
+        if (e == hipSuccess)
+            e = launch_stage_to_beam_major((const float*)stage, ds.nc, T2, d.B * K, ld, (float*)d.out + c0,
+                                           (size_t)d.C, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// lbf_beamform: the fast workers where they apply, the generic ones
+// otherwise; the staging of a whole block comes from the stream-ordered pool.
+hipError_t launch_beamform(const BlockDesc& d, hipStream_t st) {
+    if (!needs_staging(d)) return launch_beamform_direct(d, st);
+    const size_t bytes = (size_t)d.C * staging_channel_bytes(d);
+    void* stage = nullptr;
+    hipError_t e = staging_alloc(&stage, bytes, st);
     if (e != hipSuccess) return e;
-    BlockDesc ds = d;
-    ds.out = stage;
-    ds.order = 1;
-    ds.ld_row = ld;
-    e = launch_fast(ds, st);
-    // [c][t'][b k] -> [b k][t'][c]: the beam-major final order [b][k][t'][c]
-    if (e == hipSuccess) e = launch_stage_to_beam_major((const float*)stage, d.C, T2, d.B * K, ld, (float*)d.out, st);
+    e = launch_beamform_staged(d, stage, bytes, st);
     const hipError_t ef = hipFreeAsync(stage, st);
     return e != hipSuccess ? e : ef;
 }

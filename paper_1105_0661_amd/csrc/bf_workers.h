@@ -47,7 +47,7 @@ LBF_INLINE void stage_weights_f32_planes(float* pl, const BlockDesc& d, int c, i
     float2v v[R];
 #pragma unroll
     for (int k = 0; k < R; ++k)
-        v[k] = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(((uint32_t)(b0 + b1 + RS * k) * d.S + sl) * 8u), 0, 0);
+        v[k] = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)weight_off(b0 + b1 + RS * k, d.S, sl, 8), 0, 0);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int bl = b1 + RS * k;
@@ -65,12 +65,8 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
     constexpr int BYTES = sizeof(RT);
     constexpr int NOUT = PR == PR_VOLT ? 1 : 16 / TI;
     const int T = d.T, S = d.S, B = d.B;
-    const int ntiles_all = (T + kTile - 1) / kTile;
-    const int nseg = (ntiles_all + kSegTiles - 1) / kSegTiles;
-    const int seg = item % nseg;
-    const int c = item / nseg / nbg, bg = item / nseg % nbg;
-    const int tile_lo = seg * kSegTiles;
-    const int ntiles = min(kSegTiles, ntiles_all - tile_lo);
+    const ItemPos ip = item_pos(d, item, nbg);
+    const int c = ip.c, bg = ip.bg, tile_lo = ip.tile_lo, ntiles = ip.ntiles;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int r = lane & 31, h = lane >> 5;
     const int bt = wave & 3, ts = wave >> 2;
@@ -83,8 +79,7 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
     const int ngrp = min(8, ((S + 7) / 8 + 1) & ~1);
     const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
     const int T2 = PR == PR_VOLT ? T : T / TI;
-    const __amdgpu_buffer_rsrc_t ors =
-        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)T2 * d.ld_row * 4u);
+    const __amdgpu_buffer_rsrc_t ors = channel_rsrc(d, c, out_channel_bytes(d, PR, T2));
     const int trow = tile_row_sample(r);
 
     stage_weights_f32_planes(pl, d, c, b0);
@@ -106,15 +101,15 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
     auto load_quad = [&](int slot, int q4, int n) {            // stations 4 q4 .. 4 q4 + 3 of group n
         const int k = min(n / ngrp, nmine - 1), g = n % ngrp;
         const int t = min(tile_of(k) * kTile + trow, T - 1);
-        const __amdgpu_buffer_rsrc_t rs = station_group_rsrc(d.x, BYTES, 8 * g, S, c, T, stride_bytes);
+        const __amdgpu_buffer_rsrc_t rs = group_rsrc(d.x, 8 * g, S, stride_bytes);
 #pragma unroll
         for (int i = 4 * q4; i < 4 * q4 + 4; ++i)
-            ring[slot][i] = buffer_sample<XT>(rs, (uint32_t)t * BYTES + (uint32_t)i * stride_bytes);
+            ring[slot][i] = buffer_sample<XT>(rs, sample_off(i, stride_bytes, c, T, t, BYTES));
     };
     auto epi_sample = [&](const floatx16 (&prev)[4], int tprev, bool okprev, int smp, float (&sm)[NOUT][4]) {
         if (PR == PR_VOLT) {
             const int t = tprev * kTile + 16 * h + smp;
-            const uint32_t off = store_off(okprev && beam < B && t < T, ((uint32_t)beam * T + t) * 16u);
+            const uint32_t off = store_off(okprev && beam < B && t < T, volt_off(beam, T, t));
             floatx4 vv;
             vv[0] = prev[0][smp];
             vv[1] = prev[1][smp];
@@ -263,22 +258,17 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     constexpr int CPT = (NS * CPTILE + kThreadsH - 1) / kThreadsH;   // chunks per thread per step
     // item = (channel, beam group, segment of up to kSegTiles sample tiles)
     const int T = d.T;
-    const int ntiles_all = (T + kTile - 1) / kTile;
-    const int nseg = (ntiles_all + kSegTiles - 1) / kSegTiles;
-    const int seg = item % nseg;
-    const int c = item / nseg / nbg, bg = item / nseg % nbg;
-    const int tile_lo = seg * kSegTiles;                   // tiles [tile_lo, tile_lo + ntiles)
-    const int ntiles = min(kSegTiles, ntiles_all - tile_lo);
+    const ItemPos ip = item_pos(d, item, nbg);             // tiles [tile_lo, tile_lo + ntiles)
+    const int c = ip.c, bg = ip.bg, tile_lo = ip.tile_lo, ntiles = ip.ntiles;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int r = lane & 31, h = lane >> 5;
     const int bt = wave % NBT, sigma = wave / NBT;         // beam tile, sample stream
-    const int S = d.S, B = d.B, bend = d.b1;
+    const int S = d.S, bend = d.b1;
     const int beam = d.b0 + (bg * NBT + bt) * kTile + r;
     const int nsteps = (ntiles + NS - 1) / NS;
     const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
     const int T2 = PR == PR_VOLT ? T : T / TI;
-    const __amdgpu_buffer_rsrc_t ors =
-        channel_rsrc(d.out, c, PR == PR_VOLT ? (uint32_t)B * T * 16u : (uint32_t)T2 * d.ld_row * 4u);
+    const __amdgpu_buffer_rsrc_t ors = channel_rsrc(d, c, out_channel_bytes(d, PR, T2));
 
     // this wave's weights, both variants, all K-steps
     u32x4 wr[NK], wi[NK];
@@ -287,7 +277,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
 #pragma unroll
         for (int kk = 0; kk < NK; ++kk) {
             const u32x4 w = __builtin_bit_cast(
-                u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(((uint32_t)beam * S + 8 * kk + 4 * h) * 4u), 0, 0));
+                u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)weight_off(beam, S, 8 * kk + 4 * h, 4), 0, 0));
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 wr[kk][i] = neg_hi(w[i]);
@@ -302,15 +292,13 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     auto load_chunks_to = [&](int k, u32x4 (&dst)[CPT]) {
 #pragma unroll
         for (int i = 0; i < CPT; ++i) {
-            const int j = tid + kThreadsH * i;
-            const int sg = j / CPTILE, jt = j % CPTILE, s = jt / CPS, q = jt % CPS;
-            const int tile = tile_lo + min(sg + NS * k, ntiles - 1);
+            const Chunk16 ch = h_chunk(tid + kThreadsH * i, k, NS, CPTILE, CPS, tile_lo, ntiles);
             // descriptor over the whole planes of the group's stations, the
             // channel in the offset: a ragged last tile reads past the end of
             // the channel into the next one, or past the last valid station
             // (out of range: zeros), never past the array
-            const __amdgpu_buffer_rsrc_t rs = station_group_rsrc(d.x, BYTES, s & ~7, S, 0, T, stride_bytes);
-            const uint32_t off = (uint32_t)(s & 7) * stride_bytes + (uint32_t)(c * T + tile * kTile + q * SPC) * BYTES;
+            const __amdgpu_buffer_rsrc_t rs = group_rsrc(d.x, ch.s & ~7, S, stride_bytes);
+            const uint32_t off = sample_off(ch.s & 7, stride_bytes, c, T, ch.tile * kTile + ch.q * SPC, BYTES);
             dst[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
         }
     };
@@ -377,7 +365,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
             for (int smp = 16 * kk / NK; smp < 16 * (kk + 1) / NK; ++smp) {
                 if (PR == PR_VOLT) {
                     const int t = tprev * kTile + 16 * h + smp;
-                    const uint32_t off = store_off(okprev && t < T, ((uint32_t)beam * T + t) * 16u);
+                    const uint32_t off = store_off(okprev && t < T, volt_off(beam, T, t));
                     floatx4 v;
                     v[0] = prev[0][smp];
                     v[1] = prev[1][smp];

@@ -33,6 +33,8 @@ struct BlockDesc {
     int order;          // Stokes: 0 = [B][K][T'][C'] (beam-major), 1 = [C'][T'][B][K] (channel-major)
     int b0, b1;         // beams [b0, b1) taken by the fast FP16/BF16 worker (0, B for a whole block)
     int ld_row;         // Stokes order 1: floats per [C'][T'] row of [B][K] values (>= B*K)
+    int c0, nc;         // fast workers: channels [c0, c0 + nc) (0, C for a whole block); their output
+                        // holds channel c at index c - c0
 };
 
 // ---------------------------------------------------------------------------
@@ -130,7 +132,7 @@ template <> __device__ inline uint16_t f32_to_bits<CT_BF16>(float f) { return f3
 // gives lane half h the 16 consecutive samples 16h .. 16h+15 in element
 // order, so integrations over up to 16 samples stay inside one lane.
 // ---------------------------------------------------------------------------
-__device__ inline int tile_row_sample(int r) {
+__host__ __device__ inline int tile_row_sample(int r) {
     return ((r >> 2) & 1) * 16 + (r >> 3) * 4 + (r & 3);
 }
 

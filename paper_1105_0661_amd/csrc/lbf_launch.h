@@ -11,20 +11,42 @@ constexpr int kMaxBatch = 32;   // equals LBF_MAX_BATCH in include/lbf.h
 int set_error(int code, const char* fmt, ...);
 
 hipError_t launch_weights(const double* pos, int S, const double* dir, int B, double rx, double ry, double rz,
-                          const double* freq, int C, int wtype, void* w, double* tau, hipStream_t st);
+                          const double* delay, const double* freq, int C, int wtype, void* w, double* tau,
+                          hipStream_t st);
 hipError_t launch_beamform(const BlockDesc& d, hipStream_t st);
+// Staging (channel-major Stokes of the fast workers before the reorder):
+// whether a block needs it, its bytes per channel, and a launch through a
+// caller-provided buffer of cap bytes (passes of staging_chunk(d, cap)
+// channels; hipErrorInvalidValue if not one channel fits).
+bool needs_staging(const BlockDesc& d);
+size_t staging_channel_bytes(const BlockDesc& d);
+int staging_chunk(const BlockDesc& d, size_t cap);
+hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, hipStream_t st);
 hipError_t launch_beamform_generic(const BlockDesc& d, hipStream_t st);
 hipError_t launch_fast_f32(const BlockDesc& d, hipStream_t st);
 hipError_t launch_fast_f16(const BlockDesc& d, hipStream_t st);
 hipError_t launch_fast_bf16(const BlockDesc& d, hipStream_t st);
-hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, hipStream_t st);
+// stage == nullptr: staging from the stream-ordered pool; else block j has
+// cap[j] bytes of caller staging at stage[j] (blocks whose staging holds all
+// their channels share the persistent launches, the others run alone in
+// channel passes; stage[j] may be NULL for a block that needs none)
+hipError_t launch_beamform_batch(const BlockDesc* blks, int n, int* d_counter, void* const* stage, const size_t* cap,
+                                 hipStream_t st);
 hipError_t staging_alloc(void** p, size_t bytes, hipStream_t st);
+// Host-side walk of the fast workers' accesses of a block as lbf_beamform (or,
+// channel_major, lbf_beamform_channel_major) launches them, staging passes of
+// cap bytes (0: whole block) included: 0 when every access is good, 1 with a
+// message on the first bad one, 2 when the staging holds less than one
+// channel (bf_addr_check.cpp).
+int check_block_addressing(const BlockDesc& d, bool channel_major, size_t cap, int threads, uint64_t* accesses,
+                           char* msg, size_t msglen);
 hipError_t launch_stokes(const float* y, int B, int C, int T, int product, int t_int, int f_int, float* s,
                          hipStream_t st);
 hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int elem_bytes, void* out,
                             hipStream_t st);
 hipError_t launch_probe(int kind, int iters, const void* src, void* dst, size_t bytes, double* work, hipStream_t st);
-hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, int ldb, float* out, hipStream_t st);
+hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, int ldb, float* out, size_t ldo,
+                                      hipStream_t st);
 hipError_t launch_incoherent(const void* x, int xtype, int S, int C, int T, int product, int t_int, int f_int,
                              float* out, hipStream_t st);
 // superstation groups: member station indices of group g are mem[off[g] .. off[g + 1])

@@ -2,8 +2,10 @@
 //
 // Jobs (beam-forming blocks) are queued on the host and admitted in arrival
 // order when (a) fewer than max_inflight jobs are on the device and (b) their
-// device footprint -- the weights of a not-yet-cached observation, plus the
-// station samples when they arrive in host memory -- fits the caller's arena.
+// device footprint -- the weights of a not-yet-cached observation, the station
+// samples when they arrive in host memory, and the staging of their Stokes
+// products before the reorder (at most staging_cap; larger blocks run in
+// channel passes through it) -- fits the caller's arena.
 // Jobs admitted together are fused into one persistent-kernel launch
 // (lbf_beamform_batch) on the next stream of the pool, so blocks arriving
 // while others run overlap on the device.  Weights stay cached on the device
@@ -32,6 +34,7 @@
 #include <vector>
 
 #include "../../include/lbf.h"
+#include "lbf_internal.h"
 #include "lbf_launch.h"
 
 namespace {
@@ -106,7 +109,7 @@ struct WeightEntry {
 struct JobRec {
     uint64_t ticket = 0;
     lbf_job job;
-    std::vector<double> pos, dir, freq;
+    std::vector<double> pos, dir, freq, delay;   // delay: [S] residual delays, or empty
     double ref[3];
     bool has_ref = false;
     lbf_job_status st;
@@ -119,6 +122,7 @@ struct JobRec {
     int carry_in = 0, carry_out = 0, t_eff = 0;
     uint64_t cat_off = 0, cat_bytes = 0;   // [S][C][t_eff]: carried samples, then x
     bool has_cat = false;
+    uint64_t stage_off = 0, stage_bytes = 0;   // Stokes staging (0 bytes: none needed)
     struct StreamState* ss = nullptr;
 };
 
@@ -193,7 +197,7 @@ int validate_job(const lbf_job* j) {
 
 uint64_t weights_alloc_bytes(const lbf_job& j) {
     return align_up((uint64_t)j.C * j.B * j.S * weight_bytes(j.ctype)) +
-           align_up(sizeof(double) * ((uint64_t)j.S * 3 + (uint64_t)j.B * 3 + j.C));
+           align_up(sizeof(double) * ((uint64_t)j.S * 4 + (uint64_t)j.B * 3 + j.C));
 }
 
 uint64_t staging_bytes(const lbf_job& j) {
@@ -207,6 +211,28 @@ uint64_t stream_bytes(const lbf_job& j, int n) { return (uint64_t)j.S * j.C * n 
 uint64_t stream_max_bytes(const lbf_job& j) {
     if (!j.stream_id) return 0;
     return align_up(stream_bytes(j, j.T + j.t_int - 1)) + align_up(stream_bytes(j, j.t_int - 1));
+}
+
+// Stokes staging of a job: one channel's bytes for its longest block (a stream
+// block runs up to T + t_int - 1 samples), and what admission reserves: all
+// channels, or staging_cap when that is less.
+uint64_t stage_cap(const lbf_server_cfg& c) { return c.staging_cap ? c.staging_cap : (256ull << 20); }
+
+uint64_t stage_channel_bytes(const lbf_job& j) {
+    lbf_block b;
+    b.d_x = j.x; b.xtype = j.xtype;
+    b.S = j.S; b.C = j.C;
+    b.T = j.stream_id ? (j.T + j.t_int - 1) / j.t_int * j.t_int : j.T;
+    b.d_w = j.x; b.ctype = j.ctype; b.B = j.B;
+    b.product = j.product; b.t_int = j.t_int; b.f_int = j.f_int;
+    b.d_out = j.d_out;
+    return lbf::block_staging_channel_bytes(&b);
+}
+
+uint64_t stage_need(const lbf_server_cfg& c, const lbf_job& j) {
+    const uint64_t per = stage_channel_bytes(j);
+    if (per == 0) return 0;
+    return std::min<uint64_t>(per * (uint64_t)j.C, stage_cap(c));
 }
 
 char* arena_ptr(lbf_server* s, uint64_t off) { return (char*)s->cfg.d_arena + off; }
@@ -260,13 +286,14 @@ int try_admit(lbf_server* s, JobRec* r) {
     auto it = s->wcache.find(key);
     bool hit = it != s->wcache.end() && it->second.S == j.S && it->second.B == j.B && it->second.C == j.C;
     if (it != s->wcache.end() && !hit && it->second.refs > 0) return kAdmitWait;   // same id, other shape, in use
-    const uint64_t need[4] = {hit ? 0 : weights_alloc_bytes(j), staging_bytes(j), need_cat, need_tail};
-    uint64_t off[4] = {0, 0, 0, 0};
+    const uint64_t need[5] = {hit ? 0 : weights_alloc_bytes(j), staging_bytes(j), need_cat, need_tail,
+                              stage_need(s->cfg, j)};
+    uint64_t off[5] = {0, 0, 0, 0, 0};
     for (;;) {
         int k = 0;
-        for (; k < 4; ++k)
+        for (; k < 5; ++k)
             if (need[k] && !s->arena.alloc(need[k], &off[k])) break;
-        if (k == 4) break;
+        if (k == 5) break;
         for (int i = 0; i < k; ++i)
             if (need[i]) s->arena.release(off[i], need[i]);
         // evict the least recently used idle weight set (never the one we need)
@@ -303,6 +330,10 @@ int try_admit(lbf_server* s, JobRec* r) {
         r->x_bytes = need[1];
         r->staged = true;
     }
+    if (need[4]) {
+        r->stage_off = off[4];
+        r->stage_bytes = need[4];
+    }
     if (j.stream_id) {
         if (!ss) {
             ss = &s->sstate[j.stream_id];
@@ -338,6 +369,10 @@ void release_job(lbf_server* s, JobRec* r, bool failed) {
     if (r->has_cat) {
         s->arena.release(r->cat_off, r->cat_bytes);
         r->has_cat = false;
+    }
+    if (r->stage_bytes) {
+        s->arena.release(r->stage_off, r->stage_bytes);
+        r->stage_bytes = 0;
     }
     if (StreamState* ss = r->ss) {
         r->ss = nullptr;
@@ -414,14 +449,18 @@ int issue(lbf_server* s, const std::vector<JobRec*>& rs, const std::vector<lbf_b
             double* dpos = geo;
             double* ddir = geo + (size_t)j.S * 3;
             double* dfreq = ddir + (size_t)j.B * 3;
+            double* ddelay = dfreq + j.C;
             hipError_t he = hipMemcpyAsync(dpos, r->pos.data(), sizeof(double) * r->pos.size(), hipMemcpyHostToDevice, st);
             if (he == hipSuccess)
                 he = hipMemcpyAsync(ddir, r->dir.data(), sizeof(double) * r->dir.size(), hipMemcpyHostToDevice, st);
             if (he == hipSuccess)
                 he = hipMemcpyAsync(dfreq, r->freq.data(), sizeof(double) * r->freq.size(), hipMemcpyHostToDevice, st);
+            if (he == hipSuccess && !r->delay.empty())
+                he = hipMemcpyAsync(ddelay, r->delay.data(), sizeof(double) * r->delay.size(), hipMemcpyHostToDevice,
+                                    st);
             if (he != hipSuccess) return LBF_E_HIP;
-            int rc = lbf_compute_weights(dpos, j.S, ddir, j.B, r->has_ref ? r->ref : nullptr, dfreq, j.C, j.ctype, base,
-                                         nullptr, st);
+            int rc = lbf_compute_weights(dpos, j.S, ddir, j.B, r->has_ref ? r->ref : nullptr,
+                                         r->delay.empty() ? nullptr : ddelay, dfreq, j.C, j.ctype, base, nullptr, st);
             if (rc) return rc;
             if (hipEventRecord(e.ready, st) != hipSuccess) return LBF_E_HIP;
         } else {
@@ -437,12 +476,21 @@ int issue(lbf_server* s, const std::vector<JobRec*>& rs, const std::vector<lbf_b
         }
     }
     if (blocks.empty()) return LBF_OK;
+    // each block's Stokes staging is the slice its job reserved in the arena
+    std::vector<void*> stage;
+    std::vector<size_t> cap;
+    for (JobRec* r : rs) {
+        if (r->t_eff <= 0) continue;                  // as in the scheduler: no block for this job
+        stage.push_back(r->stage_bytes ? (void*)arena_ptr(s, r->stage_off) : nullptr);
+        cap.push_back((size_t)r->stage_bytes);
+    }
     bool fused = blocks.size() > 1;
     for (const lbf_block& b : blocks)
         if (b.product == LBF_VOLTAGES || b.ctype == LBF_F32 || b.ctype != blocks[0].ctype) fused = false;
-    if (fused) return lbf_beamform_batch(blocks.data(), (int)blocks.size(), st);
-    for (const lbf_block& b : blocks) {
-        int rc = lbf_beamform(&b, st);
+    if (fused) return lbf::run_batch(blocks.data(), (int)blocks.size(), stage.data(), cap.data(), st, "server");
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        int rc = stage[i] ? lbf::run_block(&blocks[i], stage[i], cap[i], st, "server")
+                          : lbf::run_block(&blocks[i], nullptr, 0, st, "server");
         if (rc) return rc;
     }
     return LBF_OK;
@@ -594,13 +642,17 @@ int lbf_server_submit(lbf_server* s, const lbf_job* job, uint64_t* ticket) {
     if (!s || !ticket) return set_error(LBF_E_INVAL, "lbf_server_submit: NULL argument");
     int rc = validate_job(job);
     if (rc) return rc;
-    if (weights_alloc_bytes(*job) + align_up(staging_bytes(*job)) + stream_max_bytes(*job) > s->cfg.arena_bytes)
+    if (stage_channel_bytes(*job) > stage_cap(s->cfg))
+        return set_error(LBF_E_NOMEM, "lbf_server_submit: one channel's Stokes staging exceeds staging_cap");
+    if (weights_alloc_bytes(*job) + align_up(staging_bytes(*job)) + stream_max_bytes(*job) +
+            align_up(stage_need(s->cfg, *job)) > s->cfg.arena_bytes)
         return set_error(LBF_E_NOMEM, "lbf_server_submit: job footprint exceeds the arena");
     std::unique_ptr<JobRec> r(new JobRec());
     r->job = *job;
     r->pos.assign(job->station_xyz, job->station_xyz + (size_t)job->S * 3);
     r->dir.assign(job->beam_dir, job->beam_dir + (size_t)job->B * 3);
     r->freq.assign(job->freq_hz, job->freq_hz + job->C);
+    if (job->station_delay) r->delay.assign(job->station_delay, job->station_delay + job->S);
     if (job->ref_dir) {
         memcpy(r->ref, job->ref_dir, sizeof(r->ref));
         r->has_ref = true;
@@ -609,6 +661,7 @@ int lbf_server_submit(lbf_server* s, const lbf_job* job, uint64_t* ticket) {
     r->job.beam_dir = nullptr;
     r->job.freq_hz = nullptr;
     r->job.ref_dir = nullptr;
+    r->job.station_delay = nullptr;
     memset(&r->st, 0, sizeof(r->st));
     r->st.state = LBF_JOB_QUEUED;
     r->st.t_submit_ns = now_ns();

@@ -46,20 +46,21 @@ class Block(ctypes.Structure):
 
 class BlockSizes(ctypes.Structure):
     _fields_ = [("input_bytes", ctypes.c_uint64), ("weight_bytes", ctypes.c_uint64),
-                ("output_bytes", ctypes.c_uint64), ("flops", ctypes.c_double)]
+                ("output_bytes", ctypes.c_uint64), ("flops", ctypes.c_double),
+                ("staging_bytes", ctypes.c_uint64), ("staging_channel_bytes", ctypes.c_uint64)]
 
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int),
                 ("n_streams", ctypes.c_int), ("queue_capacity", ctypes.c_int), ("max_batch", ctypes.c_int),
-                ("device", ctypes.c_int)]
+                ("device", ctypes.c_int), ("staging_cap", ctypes.c_uint64)]
 
 
 class Job(ctypes.Structure):
     _fields_ = [("obs_id", ctypes.c_uint64),
                 ("station_xyz", ctypes.c_void_p), ("S", ctypes.c_int),
                 ("beam_dir", ctypes.c_void_p), ("B", ctypes.c_int),
-                ("ref_dir", ctypes.c_void_p),
+                ("ref_dir", ctypes.c_void_p), ("station_delay", ctypes.c_void_p),
                 ("freq_hz", ctypes.c_void_p), ("C", ctypes.c_int),
                 ("x", ctypes.c_void_p), ("xtype", ctypes.c_int), ("T", ctypes.c_int),
                 ("x_on_host", ctypes.c_int),
@@ -80,8 +81,8 @@ _PROTOS = {
     "lbf_last_error": (ctypes.c_char_p, []),
     "lbf_version": (ctypes.c_char_p, []),
     "lbf_compute_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
-                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_beamform": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
     "lbf_beamform_channel_major": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
     "lbf_beam_major": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -101,6 +102,8 @@ _PROTOS = {
     "lbf_dedisperse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_block_footprint": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.POINTER(BlockSizes)]),
+    "lbf_check_addressing": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_uint64)]),
     "lbf_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "lbf_server_create": (ctypes.c_int, [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
@@ -205,8 +208,9 @@ def output_shape(product: int, S: int, C: int, T: int, B: int, t_int: int = 1, f
 # --------------------------------------------------------------------------
 
 def compute_weights(station_xyz, beam_dir, freq_hz, wtype: int = F32, ref_dir=None, out=None, tau=None,
-                    stream=None):
-    """w[C][B][S] (complex as a trailing pair axis) from device f64 geometry."""
+                    station_delay=None, stream=None):
+    """w[C][B][S] (complex as a trailing pair axis) from device f64 geometry;
+    ``station_delay``: device f64 [S] residual delays in seconds, or None."""
     torch = _torch()
     S, B, C = station_xyz.shape[0], beam_dir.shape[0], freq_hz.shape[0]
     if out is None:
@@ -214,9 +218,11 @@ def compute_weights(station_xyz, beam_dir, freq_hz, wtype: int = F32, ref_dir=No
     ref = None
     if ref_dir is not None:
         ref = (ctypes.c_double * 3)(*[float(v) for v in ref_dir])
+    if station_delay is not None and (station_delay.dtype != torch.float64 or tuple(station_delay.shape) != (S,)):
+        raise ValueError("station_delay must be a float64 tensor of shape (S,)")
     _check(lib().lbf_compute_weights(_dev_ptr(station_xyz, "station_xyz"), S, _dev_ptr(beam_dir, "beam_dir"), B,
-                                     ref, _dev_ptr(freq_hz, "freq_hz"), C, wtype, _dev_ptr(out, "out"),
-                                     _dev_ptr(tau, "tau"), _stream(stream)))
+                                     ref, _dev_ptr(station_delay, "station_delay"), _dev_ptr(freq_hz, "freq_hz"), C,
+                                     wtype, _dev_ptr(out, "out"), _dev_ptr(tau, "tau"), _stream(stream)))
     return out
 
 
@@ -380,6 +386,17 @@ def block_footprint(S: int, C: int, T: int, B: int, xtype: int, ctype: int, prod
     return out
 
 
+def check_addressing(S: int, C: int, T: int, B: int, xtype: int, ctype: int, product: int, t_int: int = 1,
+                     f_int: int = 1, channel_major: bool = False, staging_cap: int = 0, threads: int = 8) -> int:
+    """lbf_check_addressing on a block of these sizes (host only): raises
+    LbfError on a bad access, returns the number of accesses walked."""
+    blk = Block(d_x=1, xtype=xtype, S=S, C=C, T=T, d_w=1, ctype=ctype, B=B, product=product, t_int=t_int,
+                f_int=f_int, d_out=1)
+    n = ctypes.c_uint64()
+    _check(lib().lbf_check_addressing(ctypes.byref(blk), int(channel_major), staging_cap, threads, ctypes.byref(n)))
+    return n.value
+
+
 # --------------------------------------------------------------------------
 # streaming server
 # --------------------------------------------------------------------------
@@ -405,31 +422,31 @@ class Server:
     referenced here until the ticket is released."""
 
     def __init__(self, arena, max_inflight: int = 8, n_streams: int = 2, queue_capacity: int = 64,
-                 max_batch: int = 8, device: int = 0):
+                 max_batch: int = 8, device: int = 0, staging_cap: int = 0):
         self.arena = arena
         cfg = ServerCfg(d_arena=_dev_ptr(arena, "arena"), arena_bytes=arena.numel() * arena.element_size(),
                         max_inflight=max_inflight, n_streams=n_streams, queue_capacity=queue_capacity,
-                        max_batch=max_batch, device=device)
+                        max_batch=max_batch, device=device, staging_cap=staging_cap)
         h = ctypes.c_void_p()
         _check(lib().lbf_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
-        self._keep = {}
-        self._carry = {}     # stream_id -> samples the server carries into the stream's next block
-        self._periods = {}   # ticket -> periods its output holds
+        self._keep = {}      # ticket -> (samples, output tensor, stream block?) kept alive until release
 
     def submit(self, obs_id: int, station_xyz, beam_dir, freq_hz, x, ctype: int, product: int, t_int: int = 1,
-               f_int: int = 1, out=None, ref_dir=None, stream_id: int = 0) -> int:
+               f_int: int = 1, out=None, ref_dir=None, stream_id: int = 0, station_delay=None) -> int:
         """Queue one block.  With a non-zero ``stream_id`` the block continues
         that stream in time and its output holds (carried + T) // t_int
-        periods, carried being the samples left over from the stream's earlier
-        blocks (the same count the server keeps: the stream's total so far
-        modulo t_int)."""
+        periods, carried being the samples the server kept from the stream's
+        earlier blocks; the output buffer made here has room for the most a
+        block can complete, (t_int - 1 + T) // t_int, and ``output`` views the
+        periods the server reports for the ticket."""
         import numpy as np
         torch = _torch()
         pos = np.ascontiguousarray(station_xyz, dtype=np.float64)
         dirs = np.ascontiguousarray(beam_dir, dtype=np.float64)
         freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
         ref = None if ref_dir is None else (ctypes.c_double * 3)(*[float(v) for v in ref_dir])
+        delay = None if station_delay is None else np.ascontiguousarray(station_delay, dtype=np.float64)
         if isinstance(x, np.ndarray):
             x = torch.from_numpy(np.ascontiguousarray(x))
         on_host = not x.is_cuda
@@ -440,32 +457,34 @@ class Server:
         if pos.shape != (S, 3) or dirs.shape != (B, 3) or freq.shape != (C,):
             raise ValueError("geometry shapes %s %s %s do not match samples [S=%d][C=%d]"
                              % (pos.shape, dirs.shape, freq.shape, S, C))
-        carried = self._carry.get(stream_id, 0) if stream_id else 0
-        Tq = (carried + T) // t_int * t_int if stream_id else T
+        if delay is not None and delay.shape != (S,):
+            raise ValueError("station_delay must hold one delay per station")
+        Tq = (t_int - 1 + T) // t_int * t_int if stream_id else T
         if out is None:
             # a block that completes no period still gets a one-period buffer (never written)
             out = torch.empty(output_shape(product, S, C, max(Tq, t_int), B, t_int, f_int), dtype=torch.float32,
                               device=self.arena.device)
         job = Job(obs_id=obs_id, station_xyz=pos.ctypes.data, S=S, beam_dir=dirs.ctypes.data, B=B,
                   ref_dir=ctypes.addressof(ref) if ref is not None else None,
+                  station_delay=delay.ctypes.data if delay is not None else None,
                   freq_hz=freq.ctypes.data, C=C, x=x.data_ptr(), xtype=xtype_of(x), T=T, x_on_host=int(on_host),
                   ctype=ctype, product=product, t_int=t_int, f_int=f_int, d_out=_dev_ptr(out, "out"),
                   stream_id=stream_id)
         t = ctypes.c_uint64()
         _check(lib().lbf_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)))
-        self._keep[t.value] = (x, out)
-        self._periods[t.value] = Tq // t_int
-        if stream_id:
-            self._carry[stream_id] = (carried + T) % t_int
+        self._keep[t.value] = (x, out, bool(stream_id))
         return t.value
 
     def output(self, ticket: int):
-        """The ticket's output tensor; for a stream block that completes no
-        period, an empty view of it."""
-        out = self._keep[ticket][1]
-        if self._periods.get(ticket) == 0 and out.dim() == 4:
-            return out[:, :, :0]
-        return out
+        """The ticket's output (call after ``wait``).  For a stream block, the
+        [B][K][P][C'] view of the P periods the server wrote, P from the
+        ticket's status (empty when the block completed none)."""
+        x, out, is_stream = self._keep[ticket]
+        if not is_stream:
+            return out
+        B, K, _, C2 = out.shape
+        P = self.poll(ticket).periods
+        return out.reshape(-1)[:B * K * P * C2].view(B, K, P, C2)
 
     def poll(self, ticket: int) -> JobStatus:
         st = JobStatus()
@@ -480,14 +499,12 @@ class Server:
     def release(self, ticket: int):
         _check(lib().lbf_server_release(self._h, ticket))
         self._keep.pop(ticket, None)
-        self._periods.pop(ticket, None)
 
     def close(self):
         if self._h:
             _check(lib().lbf_server_destroy(self._h))
             self._h = None
             self._keep.clear()
-            self._periods.clear()
 
     def __enter__(self):
         return self

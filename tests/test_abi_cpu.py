@@ -61,9 +61,9 @@ def test_beamform_rejects_malformed_blocks(kw, code):
 def test_other_entry_points_validate_before_device_work():
     L = lbf.lib()
     assert L.lbf_beamform(None, None) == lbf.E_INVAL
-    assert L.lbf_compute_weights(None, 4, None, 2, None, None, 8, lbf.F32, None, None, None) == lbf.E_INVAL
-    assert L.lbf_compute_weights(1, 0, 1, 2, None, 1, 8, lbf.F32, 1, None, None) == lbf.E_INVAL
-    assert L.lbf_compute_weights(1, 4, 1, 2, None, 1, 8, 5, 1, None, None) == lbf.E_INVAL
+    assert L.lbf_compute_weights(None, 4, None, 2, None, None, None, 8, lbf.F32, None, None, None) == lbf.E_INVAL
+    assert L.lbf_compute_weights(1, 0, 1, 2, None, None, 1, 8, lbf.F32, 1, None, None) == lbf.E_INVAL
+    assert L.lbf_compute_weights(1, 4, 1, 2, None, None, 1, 8, 5, 1, None, None) == lbf.E_INVAL
     assert L.lbf_stokes(1, 2, 4, 10, lbf.STOKES_I, 3, 1, 1, None) == lbf.E_INVAL
     assert L.lbf_stokes(1, 2, 4, 12, lbf.VOLTAGES, 3, 1, 1, None) == lbf.E_INVAL
     assert L.lbf_transpose(1, 2, 3, 4, 1, 16, 2, None) == lbf.E_INVAL          # elem_bytes
@@ -127,6 +127,17 @@ def test_footprint_arithmetic():
     assert s.flops == 8 * 128 * 64 * 8192 * 768 * 2
     v = lbf.block_footprint(2, 3, 4, 5, lbf.CI8, lbf.F16, lbf.VOLTAGES)
     assert (v.input_bytes, v.weight_bytes, v.output_bytes) == (2 * 3 * 4 * 2 * 2, 3 * 5 * 2 * 4, 3 * 5 * 4 * 16)
+    # Stokes staging of the fast workers: rows of B K floats padded to 32, per (channel, period)
+    assert s.staging_channel_bytes == 48 * 512 * 4 and s.staging_bytes == 8192 * 48 * 512 * 4
+    p = lbf.block_footprint(64, 8192, 768, 488, lbf.CI8, lbf.F16, lbf.STOKES_IQUV, 16, 1)
+    assert p.staging_channel_bytes == 48 * 1952 * 4
+    i = lbf.block_footprint(40, 16, 96, 150, lbf.CI16, lbf.F16, lbf.STOKES_I, 16, 1)
+    assert i.staging_channel_bytes == 6 * 160 * 4
+    assert v.staging_bytes == 0                                                           # voltages: none
+    g = lbf.block_footprint(100, 8, 64, 40, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 1)       # > 64 stations: generic
+    assert g.staging_bytes == 0
+    f = lbf.block_footprint(40, 8, 64, 40, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 2)         # channel integration
+    assert f.staging_bytes == 0
 
 
 def _table1():

@@ -1,0 +1,68 @@
+"""Host-side walk of the fast workers' memory accesses (lbf_check_addressing,
+no GPU): for the block shapes of the GPU tests and the uneven batch's
+observations, every weight, sample and output descriptor lies inside its
+buffer, no 32-bit offset wraps, and every store the epilogue means to make
+lands inside its descriptor -- with the kernels' own address arithmetic, so a
+base moved past the data (as once by the channel in a sample descriptor) or a
+wrapping offset fails here before any kernel runs."""
+import os
+
+import pytest
+
+from paper_1105_0661_amd import lbf, synth
+
+pytestmark = pytest.mark.skipif(not os.path.exists(lbf.LIB_PATH), reason="liblbf.so not built")
+
+THREADS = max(1, min(8, os.cpu_count() or 1))
+X = {"ci8": lbf.CI8, "ci16": lbf.CI16}
+
+
+def _walk(S, C, T, B, xt, ct, prod, ti=1, fi=1, **kw):
+    n = lbf.check_addressing(S, C, T, B, X[xt], ct, prod, ti, fi, threads=THREADS, **kw)
+    assert n > 0
+    return n
+
+
+# (S, C, T, B, xtype, product, t_int): the fast-path shapes of the GPU parity
+# tests -- ragged stations (1..64), samples (32..1100), beams (1..512, beam
+# tails), every t_int, voltages and both Stokes products
+TEST_SHAPES = [(13, 5, 112, 70, "ci16", lbf.VOLTAGES, 1), (1, 3, 32, 37, "ci8", lbf.STOKES_IQUV, 4),
+               (7, 3, 33, 37, "ci16", lbf.STOKES_IQUV, 1), (33, 3, 100, 37, "ci8", lbf.STOKES_IQUV, 4),
+               (53, 3, 80, 37, "ci16", lbf.STOKES_IQUV, 16), (64, 3, 64, 37, "ci8", lbf.STOKES_I, 4),
+               (40, 2, 64, 300, "ci8", lbf.STOKES_IQUV, 16), (40, 2, 64, 385, "ci8", lbf.VOLTAGES, 1),
+               (40, 2, 64, 512, "ci16", lbf.STOKES_I, 16), (11, 10, 128, 40, "ci16", lbf.STOKES_I, 2),
+               (20, 3, 1100, 140, "ci8", lbf.STOKES_IQUV, 4), (20, 3, 1100, 50, "ci16", lbf.VOLTAGES, 1),
+               (31, 5, 48, 1, "ci16", lbf.STOKES_I, 4), (64, 16, 768, 488, "ci8", lbf.STOKES_IQUV, 16)]
+
+
+@pytest.mark.parametrize("shape", TEST_SHAPES, ids=lambda s: "S%d_C%d_T%d_B%d_%s_K%d_t%d" % s)
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16], ids=["f32", "f16"])
+def test_parity_test_shapes_stay_inside_their_buffers(shape, ctype):
+    S, C, T, B, xt, prod, ti = shape
+    _walk(S, C, T, B, xt, ctype, prod, ti)
+    if prod != lbf.VOLTAGES:
+        _walk(S, C, T, B, xt, ctype, prod, ti, channel_major=True)
+
+
+@pytest.mark.parametrize("j", range(12))
+def test_uneven_batch_observations_stay_inside_their_buffers(j):
+    js = synth.config3_jobs()[j]
+    prod = lbf.PRODUCT_NAMES[js.product]
+    C = js.nsb * js.nch
+    n = _walk(js.S, C, js.T, js.B, js.xtype, lbf.F16, prod, js.t_int)
+    # the same block through staging of a few channels at a time (the server's
+    # and the no-allocation path's channel passes)
+    per = lbf.block_footprint(js.S, C, js.T, js.B, X[js.xtype], lbf.F16, prod, js.t_int).staging_channel_bytes
+    assert _walk(js.S, C, js.T, js.B, js.xtype, lbf.F16, prod, js.t_int, staging_cap=7 * per) == n
+
+
+def test_staging_below_one_channel_is_refused():
+    per = lbf.block_footprint(40, 8, 96, 150, lbf.CI16, lbf.F16, lbf.STOKES_IQUV, 16).staging_channel_bytes
+    with pytest.raises(lbf.LbfError) as ei:
+        lbf.check_addressing(40, 8, 96, 150, lbf.CI16, lbf.F16, lbf.STOKES_IQUV, 16, staging_cap=per - 4)
+    assert ei.value.code == lbf.E_NOMEM
+
+
+def test_blocks_outside_the_fast_path_walk_nothing():
+    assert lbf.check_addressing(100, 2, 64, 30, lbf.CI8, lbf.F16, lbf.STOKES_I, 16) == 0     # > 64 stations
+    assert lbf.check_addressing(20, 4, 64, 30, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 2) == 0   # channel integration

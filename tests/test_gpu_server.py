@@ -7,7 +7,7 @@ import pytest
 
 from oracle import oracle as orc
 from paper_1105_0661_amd import lbf, synth
-from tests._util import flush, relerr, to_dev
+from tests._util import check_stokes, flush, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -82,9 +82,7 @@ def test_results_alone_equal_results_in_the_mix(ctype):
         torch.cuda.synchronize()
         assert torch.equal(a, direct), "job %d differs from lbf_beamform" % i
         ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, ti, fi, 8)
-        got = a.cpu().numpy()
-        for k in range(ref.shape[1]):
-            assert relerr(got[:, k], ref[:, k]) <= TOL[ctype], (i, k)
+        check_stokes(a.cpu().numpy(), ref, TOL[ctype], "server job %d" % i)
 
 
 def test_host_staged_input_equals_device_input():
@@ -102,13 +100,20 @@ def _align(v):
     return (v + 255) // 256 * 256
 
 
+def _footprint(blk, prod, ti, fi, ctype=lbf.F16):
+    """Arena bytes of one job: its weights (with the geometry) and its Stokes staging."""
+    fp = lbf.block_footprint(blk.S, blk.C, blk.T, blk.B, lbf.XTYPE_NAMES[blk.xtype], ctype, prod, ti, fi)
+    return (_align(fp.weight_bytes) + _align(8 * (4 * blk.S + 3 * blk.B + blk.C)), _align(fp.staging_bytes))
+
+
 def test_admission_by_footprint_evicts_idle_weights():
-    # an arena that holds one observation's weights at a time: jobs of
-    # alternating observations still all complete, with the right results
+    # an arena that holds one observation's weights (and one job's Stokes
+    # staging) at a time: jobs of alternating observations still all
+    # complete, with the right results
     torch = _torch()
     blocks = _blocks()[:2]
     xs = [to_dev(b[0].x) for b in blocks]
-    need = max(_align(b.C * b.B * b.S * 4) + _align(8 * (3 * b.S + 3 * b.B + b.C)) for b, *_ in blocks)
+    need = max(sum(_footprint(*b[:4])) for b in blocks)
     with lbf.Server(_arena(need + 256), max_inflight=4, n_streams=2, max_batch=4) as srv:
         order = [0, 1, 0, 1, 1, 0]
         tickets = [_submit(srv, *blocks[i], lbf.F16, xs[i]) for i in order]
@@ -122,10 +127,46 @@ def test_admission_by_footprint_evicts_idle_weights():
         blk, prod, ti, fi, obs = blocks[i]
         ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, ti, fi, 8)
         first = outs[order.index(i)]
-        assert relerr(first.cpu().numpy(), ref) <= TOL[lbf.F16]
+        check_stokes(first.cpu().numpy(), ref, TOL[lbf.F16], "eviction %d" % i)
         for j, o in zip(order, outs):
             if j == i:
                 assert torch.equal(o, first)
+
+
+def test_admission_waits_for_stokes_staging():
+    # two blocks of one observation (weights cached once) in an arena that
+    # holds the Stokes staging of only one of them: the second is admitted
+    # once the first has finished and given its staging back, and both
+    # results are right
+    torch = _torch()
+    blk, prod, ti, fi, obs = _blocks()[1]
+    x = to_dev(blk.x)
+    w_bytes, st_bytes = _footprint(blk, prod, ti, fi)
+    assert st_bytes > 0
+    with lbf.Server(_arena(w_bytes + st_bytes + st_bytes // 2), max_inflight=2, n_streams=2, max_batch=2) as srv:
+        flush("server staging wait")
+        tickets = [_submit(srv, blk, prod, ti, fi, obs, lbf.F16, x) for _ in range(2)]
+        sts = [srv.wait(t) for t in tickets]
+        assert all(s.state == lbf.JOB_DONE for s in sts), [(s.state, s.error) for s in sts]
+        assert sts[1].t_admit_ns >= sts[0].t_done_ns
+        outs = [srv.output(t).clone() for t in tickets]
+    # a staging cap below one channel's staging can never run that block
+    with lbf.Server(_arena(64 << 20), max_inflight=1, n_streams=1, staging_cap=256) as srv:
+        with pytest.raises(lbf.LbfError) as ei:
+            _submit(srv, blk, prod, ti, fi, obs, lbf.F16, x)
+        assert ei.value.code == lbf.E_NOMEM
+    # a cap of a few channels: the block runs in channel passes, same result
+    fp = lbf.block_footprint(blk.S, blk.C, blk.T, blk.B, lbf.XTYPE_NAMES[blk.xtype], lbf.F16, prod, ti, fi)
+    with lbf.Server(_arena(64 << 20), max_inflight=1, n_streams=1,
+                    staging_cap=5 * fp.staging_channel_bytes) as srv:
+        t = _submit(srv, blk, prod, ti, fi, obs, lbf.F16, x)
+        assert srv.wait(t).state == lbf.JOB_DONE
+        passes = srv.output(t).clone()
+    torch.cuda.synchronize()
+    ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, ti, fi, 8)
+    check_stokes(outs[0].cpu().numpy(), ref, TOL[lbf.F16], "staging wait")
+    assert torch.equal(outs[0], outs[1])
+    assert torch.equal(passes, outs[0])
 
 
 def test_queue_status_codes():
@@ -137,10 +178,12 @@ def test_queue_status_codes():
             _submit(srv, blk, prod, ti, fi, obs, lbf.F16, x)
         assert ei.value.code == lbf.E_NOMEM
     # a bounded queue refuses work rather than growing: one job on the device,
-    # one queued, blocks that take a fraction of a millisecond each
+    # one queued, blocks that take a fraction of a millisecond each (their
+    # Stokes staging capped at 16 MiB, so they run in channel passes)
     big = synth.make_block(64, 300, 8, 64, 768, "ci8", 16.0, tag=(1105, 661, 79))
     xb = to_dev(big.x)
-    with lbf.Server(_arena(64 << 20), max_inflight=1, n_streams=1, queue_capacity=1, max_batch=1) as srv:
+    with lbf.Server(_arena(64 << 20), max_inflight=1, n_streams=1, queue_capacity=1, max_batch=1,
+                    staging_cap=16 << 20) as srv:
         codes, tickets = [], []
         flush("server queue bound")
         for _ in range(32):
@@ -200,10 +243,7 @@ def test_stream_carry_equals_the_concatenated_block(ctype, prod, t_int, f_int, p
             got = torch.cat(outs, dim=2)
             torch.cuda.synchronize()
             ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, t_int, f_int, 8)
-            g = got.cpu().numpy()
-            assert g.shape == ref.shape
-            for k in range(ref.shape[1]):
-                assert relerr(g[:, k], ref[:, k]) <= TOL[ctype], (i, k)
+            check_stokes(got.cpu().numpy(), ref, TOL[ctype], "stream %d" % i)
 
 
 def test_stream_block_rules():
