@@ -129,6 +129,24 @@ typedef struct {
 int lbf_beamform(const lbf_block* blk, void* stream);
 
 /*
+ * lbf_beamform for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result bit for bit, but no call to hipMalloc, hipFree or any other
+ * allocating routine.  The Stokes staging (the fast workers' channel-major
+ * products before the reorder) comes from a fixed array of
+ * LBF_NOALLOC_SCRATCH_BYTES that the library holds in device memory, one per
+ * GPU it runs on, until the process ends; a block whose staging is larger
+ * runs through it in passes of as many channels as fit.  Every call on one
+ * GPU uses that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.  Nothing in the
+ * array needs to start at any value.
+ * Errors: as lbf_beamform; LBF_E_NOMEM when one channel's staging
+ * (T' x B x K floats, rows padded to a multiple of 32) exceeds the array.
+ */
+#define LBF_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int lbf_beamform_noalloc(const lbf_block* blk, void* stream);
+
+/*
  * The same block with the Stokes products left channel-major, the order in
  * which they are formed (each channel's beams together, Section 4.3), before
  * the reorder into the final order (Section 4.6):

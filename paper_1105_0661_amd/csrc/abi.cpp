@@ -192,6 +192,29 @@ int lbf_beamform(const lbf_block* blk, void* stream) {
     return lbf::run_block(blk, nullptr, 0, stream, "lbf_beamform");
 }
 
+int lbf_beamform_noalloc(const lbf_block* blk, void* stream) {
+    int rc = check_block(blk, "lbf_beamform_noalloc");
+    if (rc) return rc;
+    static_assert(LBF_NOALLOC_SCRATCH_BYTES == lbf::kNoAllocScratchBytes, "scratch size mismatch");
+    const lbf::BlockDesc d = to_desc(blk);
+    hipError_t e;
+    if (lbf::needs_staging(d)) {
+        const size_t per = lbf::staging_channel_bytes(d);
+        if (per > lbf::kNoAllocScratchBytes)
+            return fail(LBF_E_NOMEM, "lbf_beamform_noalloc: one channel's Stokes staging (%zu bytes: T' x B x K "
+                        "floats, rows padded to 32) exceeds the %llu-byte scratch", per,
+                        (unsigned long long)lbf::kNoAllocScratchBytes);
+        void* scratch = nullptr;
+        e = lbf::noalloc_scratch(&scratch);
+        if (e != hipSuccess) return hip_fail(e, "lbf_beamform_noalloc: scratch address");
+        e = lbf::launch_beamform_staged(d, scratch, lbf::kNoAllocScratchBytes, (hipStream_t)stream);
+    } else {
+        e = lbf::launch_beamform_direct(d, (hipStream_t)stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "lbf_beamform_noalloc");
+    return ok();
+}
+
 int lbf_beamform_channel_major(const lbf_block* blk, void* stream) {
     int rc = check_block(blk, "lbf_beamform_channel_major");
     if (rc) return rc;

@@ -142,6 +142,32 @@ hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, h
     return hipSuccess;
 }
 
+// Staging of lbf_beamform_noalloc: a fixed array in device memory, one per
+// GPU the library runs on (mapped when the library's code is loaded there,
+// held until the process ends).  In host code `scratch` names a host-side
+// stand-in, not the device array: host code only ever uses the per-device
+// address from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void** p) {
+    static std::mutex mu;
+    static void* addr[64] = {nullptr};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (addr[dev] == nullptr) {
+        void* a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));   // with this device current
+        if (e != hipSuccess) return e;
+        if (a == nullptr) return hipErrorInvalidSymbol;
+        addr[dev] = a;
+    }
+    *p = addr[dev];
+    return hipSuccess;
+}
+
 // lbf_beamform: the fast workers where they apply, the generic ones
 // otherwise; the staging of a whole block comes from the stream-ordered pool.
 hipError_t launch_beamform(const BlockDesc& d, hipStream_t st) {

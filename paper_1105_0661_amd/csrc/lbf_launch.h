@@ -22,6 +22,11 @@ bool needs_staging(const BlockDesc& d);
 size_t staging_channel_bytes(const BlockDesc& d);
 int staging_chunk(const BlockDesc& d, size_t cap);
 hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, hipStream_t st);
+hipError_t launch_beamform_direct(const BlockDesc& d, hipStream_t st);   // blocks that need no staging
+// The fixed staging array of lbf_beamform_noalloc on the current device: its
+// device address (looked up once per device, with that device current).
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+hipError_t noalloc_scratch(void** p);
 hipError_t launch_beamform_generic(const BlockDesc& d, hipStream_t st);
 hipError_t launch_fast_f32(const BlockDesc& d, hipStream_t st);
 hipError_t launch_fast_f16(const BlockDesc& d, hipStream_t st);

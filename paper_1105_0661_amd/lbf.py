@@ -85,6 +85,7 @@ _PROTOS = {
                                            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_beamform": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
     "lbf_beamform_channel_major": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
+    "lbf_beamform_noalloc": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
     "lbf_beam_major": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_beamform_batch": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.c_void_p]),
@@ -244,6 +245,19 @@ def beamform(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, strea
         out = torch.empty(output_shape(product, S, C, T, B, t_int, f_int), dtype=torch.float32, device=x.device)
     blk = make_block(x, w, product, t_int, f_int, out)
     _check(lib().lbf_beamform(ctypes.byref(blk), _stream(stream)))
+    return out
+
+
+def beamform_noalloc(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, stream=None):
+    """``beamform`` through lbf_beamform_noalloc: the library allocates
+    nothing (pass ``out`` to allocate nothing here either)."""
+    torch = _torch()
+    S, C, T = x.shape[0], x.shape[1], x.shape[2]
+    B = w.shape[1]
+    if out is None:
+        out = torch.empty(output_shape(product, S, C, T, B, t_int, f_int), dtype=torch.float32, device=x.device)
+    blk = make_block(x, w, product, t_int, f_int, out)
+    _check(lib().lbf_beamform_noalloc(ctypes.byref(blk), _stream(stream)))
     return out
 
 
