@@ -284,10 +284,14 @@ int lbf_dedisperse(const void* d_y, int C, int B, int T, int n_fft, const void* 
  *   kind 2: a 16-byte copy of `bytes` (rounded down to 16) from d_src to
  *           d_dst (device buffers, not overlapping); *work = bytes moved
  *           (read + write).
- * d_dst must be a device buffer of at least 1024 bytes for kinds 0 and 1 (it
- * is never written).  The caller times the call with events on `stream`.
+ *   kind 3: a 16-byte read stream of `bytes` (rounded down to 16) of d_src;
+ *           *work = bytes read.  d_dst (at least 1024 bytes) takes at most a
+ *           word per thread index, where the xor of a thread's data equals a
+ *           fixed key.
+ * d_dst must be a device buffer of at least 1024 bytes for kinds 0, 1 and 3
+ * (kinds 0 and 1 never write it).  The caller times the call with events on `stream`.
  * Errors: LBF_E_INVAL for an unknown kind, iters < 1, NULL pointers or
- * bytes < 16 for a copy.
+ * bytes < 16 for a copy or a read.
  */
 int lbf_probe(int kind, int iters, const void* d_src, void* d_dst, uint64_t bytes, double* work, void* stream);
 

@@ -371,9 +371,10 @@ int lbf_dedisperse(const void* d_y, int C, int B, int T, int n_fft, const void* 
 
 int lbf_probe(int kind, int iters, const void* d_src, void* d_dst, uint64_t bytes, double* work, void* stream) {
     if (!work || !d_dst) return fail(LBF_E_INVAL, "lbf_probe: NULL pointer");
-    if (kind < 0 || kind > 2) return fail(LBF_E_INVAL, "lbf_probe: unknown kind %d", kind);
+    if (kind < 0 || kind > 3) return fail(LBF_E_INVAL, "lbf_probe: unknown kind %d", kind);
     if (kind < 2 && iters < 1) return fail(LBF_E_INVAL, "lbf_probe: iters must be >= 1");
-    if (kind == 2 && (!d_src || bytes < 16)) return fail(LBF_E_INVAL, "lbf_probe: copy needs a source and >= 16 bytes");
+    if (kind >= 2 && (!d_src || bytes < 16))
+        return fail(LBF_E_INVAL, "lbf_probe: copy and read need a source and >= 16 bytes");
     hipError_t e = lbf::launch_probe(kind, iters, d_src, d_dst, (size_t)bytes, work, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lbf_probe");
     return LBF_OK;

@@ -1,5 +1,6 @@
 // probe.hip -- peak probes for roofline reporting: register-only MFMA loops
-// (the instruction forms the contraction uses) and a plain device copy.
+// (the instruction forms the contraction uses), a plain device copy and a
+// read-only stream.
 // They measure what this device sustains, beside the datasheet figures.
 #include "lbf_device.h"
 #include "lbf_launch.h"
@@ -60,6 +61,28 @@ __global__ __launch_bounds__(256) void probe_copy_kernel(const floatx4* __restri
     }
 }
 
+// 16-byte read stream, four loads per thread in flight, folded into an xor
+// that is stored only where it equals `key` (so the loads stay live; dst
+// takes at most one word per thread index, 256 words)
+__global__ __launch_bounds__(256) void probe_read_kernel(const floatx4* __restrict__ src, uint32_t* __restrict__ dst,
+                                                         size_t n4, uint32_t key) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    uint32_t acc = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += 4 * stride) {
+        floatx4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = floatx4{};
+            if (i + u * stride < n4) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            acc ^= __float_as_uint(v[u][0]) ^ __float_as_uint(v[u][1]) ^ __float_as_uint(v[u][2]) ^
+                   __float_as_uint(v[u][3]);
+    }
+    if (acc == key) dst[threadIdx.x] = acc;
+}
+
 hipError_t launch_probe(int kind, int iters, const void* src, void* dst, size_t bytes, double* work, hipStream_t st) {
     int dev = 0, cus = 256;
     hipError_t e = hipGetDevice(&dev);
@@ -76,6 +99,12 @@ hipError_t launch_probe(int kind, int iters, const void* src, void* dst, size_t 
         return hipGetLastError();
     }
     const size_t n4 = bytes / 16;
+    if (kind == 3) {
+        hipLaunchKernelGGL(probe_read_kernel, dim3((unsigned)(cus * 32)), dim3(256), 0, st, (const floatx4*)src,
+                           (uint32_t*)dst, n4, 0x9e3779b9u);
+        *work = (double)(n4 * 16);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(probe_copy_kernel, dim3((unsigned)(cus * 32)), dim3(256), 0, st, (const floatx4*)src,
                        (floatx4*)dst, n4);
     *work = 2.0 * (double)(n4 * 16);

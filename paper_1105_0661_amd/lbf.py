@@ -415,7 +415,7 @@ def check_addressing(S: int, C: int, T: int, B: int, xtype: int, ctype: int, pro
 # streaming server
 # --------------------------------------------------------------------------
 
-PROBE_MFMA_F16, PROBE_MFMA_F32, PROBE_COPY = 0, 1, 2
+PROBE_MFMA_F16, PROBE_MFMA_F32, PROBE_COPY, PROBE_READ = 0, 1, 2, 3
 
 
 def probe(kind: int, iters: int = 1, src=None, dst=None, stream=None) -> float:

@@ -98,7 +98,8 @@ def test_other_entry_points_validate_before_device_work():
     arr[1] = _block(ctype=lbf.F16, product=lbf.VOLTAGES, t_int=1)
     assert L.lbf_beamform_batch(arr, 2, None) == lbf.E_UNSUPPORTED
     work = ctypes.c_double()
-    assert L.lbf_probe(3, 1, None, 1, 0, ctypes.byref(work), None) == lbf.E_INVAL        # unknown kind
+    assert L.lbf_probe(4, 1, None, 1, 0, ctypes.byref(work), None) == lbf.E_INVAL        # unknown kind
+    assert L.lbf_probe(lbf.PROBE_READ, 1, None, 1, 64, ctypes.byref(work), None) == lbf.E_INVAL   # no source
     assert L.lbf_probe(lbf.PROBE_MFMA_F16, 0, None, 1, 0, ctypes.byref(work), None) == lbf.E_INVAL
     assert L.lbf_probe(lbf.PROBE_MFMA_F32, 1, None, 1, 0, None, None) == lbf.E_INVAL
     assert L.lbf_probe(lbf.PROBE_COPY, 1, None, 1, 64, ctypes.byref(work), None) == lbf.E_INVAL

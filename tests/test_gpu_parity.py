@@ -482,3 +482,8 @@ def test_probe_copy_is_a_copy_and_mfma_probes_report_their_work():
         cus = torch.cuda.get_device_properties(0).multi_processor_count
         assert w == 2 * cus * 4 * 3 * 8 * flop
     assert torch.count_nonzero(sink).item() == 0          # the probes never write their sink
+    zeros = torch.zeros(1 << 20, dtype=torch.float32, device="cuda:0")
+    w = lbf.probe(lbf.PROBE_READ, 1, zeros, sink)
+    torch.cuda.synchronize()
+    assert w == zeros.numel() * 4
+    assert torch.count_nonzero(sink).item() == 0          # the xor of zeros never equals the key
