@@ -212,12 +212,14 @@ def superstations(lbf, torch, dev, steps, warmup, mp):
     return r
 
 
-def channelizer(lbf, torch, dev, steps, warmup, mp):
+def channelizer(lbf, torch, dev, steps, warmup, mp, geo=None):
     """The channeliser ahead of the one-second block: 64 stations x 32
     subbands of 196608 complex int16 samples (1.0066 s at 195 kHz), 256
     channels per subband -> the block's [64][8192][768][2] channels in
     complex f32.  Seeded uniform int16 samples generated on the device.
-    HBM-bound: every sample read once, every channel sample written once."""
+    HBM-bound: every sample read once, every channel sample written once.
+    With the block's geometry, also the chain channelise -> beam form (128
+    beams, Stokes IQUV x16) on those complex f32 channels, FP16 MFMA and FP32."""
     S, NSB, nch = 64, 32, 256
     T_sb = 768 * nch
     gen = torch.Generator(device=dev).manual_seed(1105661)
@@ -240,6 +242,31 @@ def channelizer(lbf, torch, dev, steps, warmup, mp):
          "input_Gbps": S * NSB * T_sb * 64 / (ms / 1e3) / 1e9}
     if mp:
         r["frac_of_measured_hbm"] = gbps / max(mp["hbm_GBps"], mp["hbm_read_GBps"])
+    if geo is not None:
+        pos, dirs, freq, ref = geo
+        B = dirs.shape[0]
+        chain = {}
+        for name, ct in (("f16", lbf.F16), ("f32", lbf.F32)):
+            w = lbf.compute_weights(pos, dirs, freq, ct, ref_dir=ref)
+            bf = torch.empty((B, 4, 48, NSB * nch), dtype=torch.float32, device=dev)
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nrep)]
+            for i in range(nrep):
+                ev[i][0].record()
+                lbf.channelize(x, nch, out=out)
+                ev[i][1].record()
+                lbf.beamform(out, w, lbf.STOKES_IQUV, 16, 1, out=bf)
+                ev[i][2].record()
+            torch.cuda.synchronize()
+            bms = float(np.mean([ev[i][1].elapsed_time(ev[i][2]) for i in range(warmup, nrep)]))
+            tms = float(np.mean([ev[i][0].elapsed_time(ev[i][2]) for i in range(warmup, nrep)]))
+            fpc = lbf.block_footprint(S, NSB * nch, 768, B, lbf.CF32, ct, lbf.STOKES_IQUV, 16, 1)
+            chain[name] = {"beamform_ms": bms, "chain_ms": tms,
+                           "beamform_hbm_GBps": (fpc.input_bytes + fpc.weight_bytes + fpc.output_bytes)
+                           / (bms / 1e3) / 1e9,
+                           "beam_samples_per_s": B * NSB * nch * 768 / (tms / 1e3)}
+            del w, bf
+        r["channelise_then_beamform"] = dict(chain, workload="channelise (above) -> lbf_beamform on the complex f32 "
+                                                             "channels: 128 beams, Stokes IQUV x16, final order")
     del x, out
     return r
 
@@ -274,6 +301,78 @@ def dedispersion(lbf, torch, dev, steps, warmup, mp):
     if mp:
         r["frac_of_measured_hbm"] = gbps / max(mp["hbm_GBps"], mp["hbm_read_GBps"])
     del y, h, out
+    return r
+
+
+def pulsar_chain(lbf, torch, synth, dev, steps, warmup, mp):
+    """Table 1 case E end to end on one GPU's share of the subbands: 64
+    stations of complex int16 (32 subbands x 16 channels of 12.2 kHz, 3 x
+    4096 samples = 1.007 s), 10 tied-array beams formed as voltages (FP16
+    MFMA), channel-level dedispersion (4096-point FFT, chirp, inverse FFT),
+    Stokes IQUV at full time resolution (case E's 6.2 Gb/s per beam) and the
+    final per-beam order.  Fused: lbf_dedisperse_stokes keeps the dedispersed
+    voltages on chip; unfused: lbf_dedisperse, lbf_stokes.  Both end with
+    lbf_transpose, and their outputs agree."""
+    S, B, nsb, nch, n = 64, 10, 32, 16, 4096
+    T = 3 * n
+    blk = synth.make_block(S, B, nsb, nch, T, "ci16", 64.0, tag=(1105, 661, 5), n_tones=2, tone_amp=64.0,
+                           threads=16)
+    x = torch.from_numpy(blk.x).to(dev)
+    del blk.x
+    C = blk.C
+    w = lbf.compute_weights(torch.from_numpy(blk.station_xyz).to(dev), torch.from_numpy(blk.beam_dir).to(dev),
+                            torch.from_numpy(blk.freq_hz).to(dev), lbf.F16, ref_dir=blk.ref_dir)
+    gen = torch.Generator().manual_seed(1105662)
+    ph = torch.rand((C, n), generator=gen, dtype=torch.float64) * 2 * np.pi
+    h = torch.stack([torch.cos(ph), torch.sin(ph)], dim=-1).float().to(dev)
+    y = torch.empty((C, B, T, 2, 2), device=dev)
+    yd = torch.empty_like(y)
+    s = torch.empty((C, B, T, 4), device=dev)
+    s2 = torch.empty_like(s)
+    o = torch.empty((B, 4, T, C), device=dev)
+    o2 = torch.empty_like(o)
+    nrep = warmup + steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(8)] for _ in range(nrep)]
+    for i in range(nrep):
+        e = ev[i]
+        e[0].record()
+        lbf.beamform(x, w, lbf.VOLTAGES, out=y)
+        e[1].record()
+        lbf.dedisperse_stokes(y, h, n, lbf.STOKES_IQUV, 1, out=s)
+        e[2].record()
+        lbf.transpose(s, out=o)
+        e[3].record()
+        lbf.beamform(x, w, lbf.VOLTAGES, out=y)
+        e[4].record()
+        lbf.dedisperse(y, h, n, out=yd)
+        e[5].record()
+        lbf.stokes(yd, lbf.STOKES_IQUV, 1, 1, out=s2)
+        e[6].record()
+        lbf.transpose(s2, out=o2)
+        e[7].record()
+    torch.cuda.synchronize()
+
+    def span(a, b):
+        return float(np.mean([ev[i][a].elapsed_time(ev[i][b]) for i in range(warmup, nrep)]))
+
+    fused = {"beamform_ms": span(0, 1), "dedisperse_stokes_ms": span(1, 2), "transpose_ms": span(2, 3),
+             "total_ms": span(0, 3)}
+    unf = {"beamform_ms": span(3, 4), "dedisperse_ms": span(4, 5), "stokes_ms": span(5, 6),
+           "transpose_ms": span(6, 7), "total_ms": span(3, 7)}
+    vb = C * B * T * 16                                     # voltages, or Stokes IQUV at full resolution
+    dd_bytes = vb + C * n * 8 + vb                          # fused: voltages in, Stokes out
+    diff = float((o - o2).norm() / o2.norm())
+    r = {"workload": "Table 1 case E share: 64 stations ci16, 512 channels (32 x 16 of 12.2 kHz), 12288 samples, "
+                     "10 beams: voltages (FP16 MFMA) -> dedispersion (4096-point) -> Stokes IQUV x1 -> final order",
+         "fused": fused, "unfused": unf, "rel_diff_fused_vs_unfused": diff,
+         "beam_samples_per_s": C * B * T / (fused["total_ms"] / 1e3),
+         "input_Gbps": S * C * T * 8 * 8 / (fused["total_ms"] / 1e3) / 1e9,
+         "dedisperse_stokes_hbm_GBps": dd_bytes / (fused["dedisperse_stokes_ms"] / 1e3) / 1e9,
+         "realtime_factor": (T * nch / SUBBAND_HZ) / (fused["total_ms"] / 1e3)}
+    if mp:
+        r["dedisperse_stokes_frac_of_measured_hbm"] = r["dedisperse_stokes_hbm_GBps"] / max(mp["hbm_GBps"],
+                                                                                            mp["hbm_read_GBps"])
+    del x, w, h, y, yd, s, s2, o, o2
     return r
 
 
@@ -591,7 +690,7 @@ def main():
 
     # ---------------- the 488-beam precision block (MFMA-bound) ----------------
     extra = None
-    batch_res = serve_res = unfused_res = inc_res = dd_res = ch_res = ss_res = None
+    batch_res = serve_res = unfused_res = inc_res = dd_res = ch_res = ss_res = pc_res = None
     if not a.no_extra and not only:
         unfused_res = unfused(lbf, torch, x, geo, 1024, max(3, a.steps // 4), 1)
         log("unfused chain: %s" % unfused_res)
@@ -599,7 +698,9 @@ def main():
         log("incoherent beam: %s" % inc_res)
         dd_res = dedispersion(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp)
         log("dedispersion: %s" % dd_res)
-        ch_res = channelizer(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp)
+        pc_res = pulsar_chain(lbf, torch, synth, dev, max(5, a.steps // 2), a.warmup, mp)
+        log("pulsar chain (case E): %s" % pc_res)
+        ch_res = channelizer(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp, geo)
         log("channeliser: %s" % ch_res)
         ss_res = superstations(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp)
         log("superstations: %s" % ss_res)
@@ -705,6 +806,8 @@ def main():
         line["incoherent_beam"] = inc_res
     if dd_res:
         line["dedispersion"] = dd_res
+    if pc_res:
+        line["pulsar_chain_case_E"] = pc_res
     if ch_res:
         line["channeliser"] = ch_res
     if ss_res:

@@ -275,6 +275,23 @@ int lbf_dedisperse(const void* d_y, int C, int B, int T, int n_fft, const void* 
                    void* stream);
 
 /*
+ * Channel-level dedispersion (Section 4.4) followed by Stokes detection
+ * (Section 4.5) and integration over t_int consecutive samples, in one pass:
+ * the dedispersed voltages stay on chip.  Equals lbf_dedisperse and then
+ * lbf_stokes (f_int = 1) up to FP32 rounding.
+ *   d_y     complex f32 [C][B][T][2];  d_chirp complex f32 [C][n_fft]
+ *   d_s     f32 [C][B][T'][K], T' = T / t_int (the layout of lbf_stokes;
+ *           lbf_transpose gives the final order); must not overlap d_y or d_chirp
+ * n_fft as lbf_dedisperse; product STOKES_I or STOKES_IQUV; t_int a power of
+ * two up to min(n_fft, 64 max(1, n_fft / 256)) (1024 at n_fft = 4096).
+ * Errors: LBF_E_INVAL for sizes < 1, an unsupported n_fft, product or t_int,
+ * T not a multiple of n_fft, NULL, misaligned or overlapping buffers, or more
+ * than 2^31 - 1 blocks.
+ */
+int lbf_dedisperse_stokes(const void* d_y, int C, int B, int T, int n_fft, const void* d_chirp, int product,
+                          int t_int, float* d_s, void* stream);
+
+/*
  * Peak probes, for reporting the kernels' rooflines against what this device
  * sustains beside the datasheet figures (not part of the beam former).
  *   kind 0: a register-only loop of MFMA 32x32x16 f16 (the FP16 contraction's

@@ -369,6 +369,35 @@ int lbf_dedisperse(const void* d_y, int C, int B, int T, int n_fft, const void* 
     return ok();
 }
 
+int lbf_dedisperse_stokes(const void* d_y, int C, int B, int T, int n_fft, const void* d_chirp, int product, int t_int,
+                          float* d_s, void* stream) {
+    if (C < 1 || B < 1 || T < 1) return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: sizes must be >= 1");
+    if (n_fft != 8 && n_fft != 64 && n_fft != 512 && n_fft != 4096)
+        return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: n_fft must be 8, 64, 512 or 4096 (got %d)", n_fft);
+    if (T % n_fft) return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: T=%d is not a multiple of n_fft=%d", T, n_fft);
+    if (product != LBF_STOKES_I && product != LBF_STOKES_IQUV)
+        return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: product must be STOKES_I or STOKES_IQUV (got %d)", product);
+    const int tmax = 64 * (n_fft >= 256 ? n_fft / 256 : 1);
+    if (!is_pow2(t_int) || t_int > n_fft || t_int > tmax)
+        return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: t_int=%d must be a power of two up to %d", t_int,
+                    n_fft < tmax ? n_fft : tmax);
+    if (!d_y || !d_chirp || !d_s) return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: NULL device pointer");
+    if (((uintptr_t)d_y | (uintptr_t)d_chirp | (uintptr_t)d_s) & 15)
+        return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: buffers must be 16-byte aligned");
+    if ((long long)C * B * (T / n_fft) > 0x7fffffffLL)
+        return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: too many blocks");
+    const size_t ybytes = (size_t)C * B * T * 16, sbytes = (size_t)C * B * (T / t_int) * product * 4;
+    const char* a = (const char*)d_y;
+    const char* o = (const char*)d_s;
+    if (a < o + sbytes && o < a + ybytes) return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: input and output overlap");
+    const char* h = (const char*)d_chirp;
+    if (h < o + sbytes && o < h + (size_t)C * n_fft * 8)
+        return fail(LBF_E_INVAL, "lbf_dedisperse_stokes: chirp and output overlap");
+    hipError_t e = lbf::launch_dedisperse_stokes(d_y, C, B, T, n_fft, d_chirp, product, t_int, d_s, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbf_dedisperse_stokes");
+    return ok();
+}
+
 int lbf_probe(int kind, int iters, const void* d_src, void* d_dst, uint64_t bytes, double* work, void* stream) {
     if (!work || !d_dst) return fail(LBF_E_INVAL, "lbf_probe: NULL pointer");
     if (kind < 0 || kind > 3) return fail(LBF_E_INVAL, "lbf_probe: unknown kind %d", kind);

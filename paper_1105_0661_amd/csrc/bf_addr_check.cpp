@@ -96,7 +96,7 @@ void walk_h(Walk& w, const BlockDesc& d, int lo, int hi) {
     const uint32_t stride = (uint32_t)stride64;
     if (stride != stride64) return w.fail("station stride does not fit 32 bits");
     const int NS = fast_h_streams(d), NK = fast_h_ksteps(d.S), NBT = 8 / NS;
-    const int SPC = d.xtype == XT_CI8 ? 4 : 2, CPS = kTile / SPC, CPTILE = 8 * NK * CPS;
+    const int SPC = 16 / bytes, CPS = kTile / SPC, CPTILE = 8 * NK * CPS;
     const int CPT = (NS * CPTILE + kThreadsH - 1) / kThreadsH;
     int nbg;
     const int items = block_items_fast_h(d, &nbg);

@@ -25,7 +25,9 @@ static_assert(sizeof(BatchArgs) <= 4096, "kernel argument block");
 
 // Items of t_int = 16 Stokes blocks (the common integration) run the fast
 // workers; everything else in a batch runs the generic ones.
-__host__ __device__ inline bool batch_fast(const BlockDesc& d) { return fast_path(d) && d.t_int == 16; }
+__host__ __device__ inline bool batch_fast(const BlockDesc& d) {
+    return fast_path(d) && d.t_int == 16 && d.xtype != XT_CF32;
+}
 
 // variant index of a fast block: ((xtype, product), K-steps 4..8, streams)
 constexpr int kBatchVariants = 2 * 2 * 5 * 2;

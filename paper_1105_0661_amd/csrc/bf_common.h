@@ -597,8 +597,12 @@ LBF_INLINE WaveTiles wave_tiles(int wave, int T, int t_int) {
 }
 
 // Sample streams of the fast FP16/BF16 worker: one for more than 128 beams
-// (work items of 256 beams), else two (items of 128 beams).
-__host__ __device__ inline int fast_h_streams(const BlockDesc& d) { return d.b1 - d.b0 > 128 ? 1 : 2; }
+// (work items of 256 beams), else two (items of 128 beams).  Complex f32
+// samples always take one: a 16-byte chunk holds a single sample, and the
+// loaders of two streams would need twice the registers.
+__host__ __device__ inline int fast_h_streams(const BlockDesc& d) {
+    return d.xtype == XT_CF32 || d.b1 - d.b0 > 128 ? 1 : 2;
+}
 
 // K-steps of 8 stations of the fast FP16/BF16 worker: 4 to 8, the fewest that hold the stations (at least 4)
 __host__ __device__ inline int fast_h_ksteps(int S) { return S <= 32 ? 4 : (S + 7) / 8; }
@@ -650,12 +654,12 @@ __host__ __device__ constexpr int staging_ld(int B, int K) { return (B * K + 31)
 
 __host__ __device__ constexpr int sample_bytes(int xtype) { return xtype == XT_CI8 ? 4 : xtype == XT_CI16 ? 8 : 16; }
 
-// The fast workers take up to 64 stations of complex int8/int16 samples,
+// The fast workers take up to 64 stations of complex int8/int16/f32 samples,
 // voltages or Stokes with t_int <= 16 and no channel integration, and 8
 // stations' worth of one channel-major station plane addressable with 31-bit
 // byte offsets.  Everything else runs the generic workers.
 __host__ __device__ inline bool fast_path(const BlockDesc& d) {
-    if (d.S > kStationChunk || d.xtype == XT_CF32) return false;
+    if (d.S > kStationChunk) return false;
     if (d.product != PR_VOLT && (d.t_int > 16 || d.f_int != 1)) return false;
     // one channel's output (addressed with 32-bit buffer offsets, 2^31 = "no store")
     const double out_ch = d.product == PR_VOLT ? 16.0 * d.B * (double)d.T
@@ -686,6 +690,9 @@ template <> LBF_INLINE shortx4 buffer_sample<XT_CI16>(__amdgpu_buffer_rsrc_t r, 
     typedef int int2v __attribute__((ext_vector_type(2)));
     const int2v v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
     return __builtin_bit_cast(shortx4, v);
+}
+template <> LBF_INLINE floatx4 buffer_sample<XT_CF32>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
 }
 
 }  // namespace lbf

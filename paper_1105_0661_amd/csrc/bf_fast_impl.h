@@ -60,8 +60,12 @@ inline void launch_h_ns(const BlockDesc& d, int nbg, int n, hipStream_t st) {
 
 template <int XT, int CT, int PR, int TI>
 inline hipError_t launch_h_k(const BlockDesc& d, int nbg, int n, hipStream_t st) {
-    if (fast_h_streams(d) == 1) launch_h_ns<XT, CT, PR, TI, 1>(d, nbg, n, st);
-    else launch_h_ns<XT, CT, PR, TI, 2>(d, nbg, n, st);
+    if constexpr (XT == XT_CF32) {
+        launch_h_ns<XT, CT, PR, TI, 1>(d, nbg, n, st);      // complex f32: one stream (fast_h_streams)
+    } else {
+        if (fast_h_streams(d) == 1) launch_h_ns<XT, CT, PR, TI, 1>(d, nbg, n, st);
+        else launch_h_ns<XT, CT, PR, TI, 2>(d, nbg, n, st);
+    }
     return hipGetLastError();
 }
 
@@ -91,8 +95,9 @@ inline hipError_t launch_fast_h(const BlockDesc& d, hipStream_t st) {
     for (int p = 0; p < np; ++p) {
         int nbg;
         const int n = block_items_fast_h(part[p], &nbg);
-        const hipError_t e = d.xtype == XT_CI8 ? launch_h_xt<XT_CI8, CT>(part[p], nbg, n, st)
-                                               : launch_h_xt<XT_CI16, CT>(part[p], nbg, n, st);
+        const hipError_t e = d.xtype == XT_CI8    ? launch_h_xt<XT_CI8, CT>(part[p], nbg, n, st)
+                             : d.xtype == XT_CI16 ? launch_h_xt<XT_CI16, CT>(part[p], nbg, n, st)
+                                                  : launch_h_xt<XT_CF32, CT>(part[p], nbg, n, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -247,6 +247,27 @@ template <int CT> struct Chunk<XT_CI16, CT> {
     }
 };
 
+// complex f32: one sample per 16-byte chunk, rounded to the operand type
+// (round-to-nearest-even)
+template <> struct Chunk<XT_CF32, CT_F16> {
+    static constexpr int samples = 1;
+    LBF_INLINE static void xy(const u32x4& v, int, uint32_t& fx, uint32_t& fy) {
+        const floatx4 f = __builtin_bit_cast(floatx4, v);
+        const halfx2 hx = {(_Float16)f[0], (_Float16)f[1]};
+        const halfx2 hy = {(_Float16)f[2], (_Float16)f[3]};
+        fx = __builtin_bit_cast(uint32_t, hx);
+        fy = __builtin_bit_cast(uint32_t, hy);
+    }
+};
+template <> struct Chunk<XT_CF32, CT_BF16> {
+    static constexpr int samples = 1;
+    LBF_INLINE static void xy(const u32x4& v, int, uint32_t& fx, uint32_t& fy) {
+        const floatx4 f = __builtin_bit_cast(floatx4, v);
+        fx = pack_bf16(f[0], f[1]);
+        fy = pack_bf16(f[2], f[3]);
+    }
+};
+
 template <int XT, int CT, int PR, int TI, int NK, int NS>
 LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at) {
     typedef typename MfmaH<CT>::vec V;
@@ -330,7 +351,9 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     // the last two slices.
     const int trow = tile_row_sample(r);
     const int sw = a_swz(trow);
-    constexpr bool PIPE = !(XT == XT_CI16 && NS == 2);     // two accumulator sets
+    // two accumulator sets, unless the loaders' registers leave no room
+    // (complex int16 with two streams, more than two chunks per thread)
+    constexpr bool PIPE = !(XT == XT_CI16 && NS == 2) && CPT <= 2;
     constexpr int NOUT = PR == PR_VOLT ? 1 : 16 / TI;
     auto step = [&](int k, floatx16 (&acc)[4], const floatx16 (&prev)[4]) {
         load_chunks(k + 1);
@@ -416,8 +439,8 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     for (int i = 0; i < CPT; ++i) store_chunk(0, i);
     __syncthreads();
     if (!PIPE) {
-        // one accumulator set (complex int16 with two streams: the loaders'
-        // registers leave no room for a second): MFMAs, then the epilogue.
+        // one accumulator set (the loaders' registers leave no room for a
+        // second): MFMAs, then the epilogue.
         // The samples of step j sit in rr[j % 2], loaded two steps ahead.
         floatx16 acc[4];
         u32x4 rr[2][CPT];

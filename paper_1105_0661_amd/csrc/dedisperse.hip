@@ -17,6 +17,9 @@
 // reads HBM and the last writes HBM, each as 16-byte vectors (both
 // polarisations of one sample) of consecutive samples.  Roofline: HBM (each
 // voltage is read and written once; the passes in between stay on chip).
+// The Stokes form (Section 4.5 after Section 4.4) keeps the last backward
+// pass in LDS and forms Stokes parameters integrated over t_int consecutive
+// samples from there, so the dedispersed voltages never reach HBM.
 #include "fft_device.h"
 #include "lbf_launch.h"
 
@@ -51,7 +54,8 @@ __host__ __device__ constexpr int lds_words() { return N + N / 32; }
 
 // One Stockham pass over both polarisations.  SRC 0: the block in HBM,
 // 1: LDS.  DST 0: LDS, 1: LDS after the chirp product and conjugation (last
-// forward pass), 2: HBM after conjugation and 1/N (last backward pass).
+// forward pass), 2: HBM after conjugation and 1/N (last backward pass), 3:
+// LDS after conjugation and 1/N (last backward pass of the Stokes form).
 template <int N, int SRC, int DST>
 __device__ __forceinline__ void dd_pass(int Ns, cfl* buf, const floatx4* __restrict__ yb, const cfl* __restrict__ hc,
                                         floatx4* __restrict__ ob) {
@@ -115,6 +119,11 @@ __device__ __forceinline__ void dd_pass(int Ns, cfl* buf, const floatx4* __restr
                 b = cmul(b, w);
                 a.y = -a.y;
                 b.y = -b.y;
+            }
+            if (DST == 3) {
+                constexpr float inv = 1.0f / (float)N;      // a power of two: exact
+                a = mk(a.x * inv, -a.y * inv);
+                b = mk(b.x * inv, -b.y * inv);
             }
             if (DST == 2) {
                 constexpr float inv = 1.0f / (float)N;      // a power of two: exact
@@ -190,6 +199,11 @@ __device__ __forceinline__ void dd_pass16(int Ns, cfl* buf, const floatx4* __res
             a.y = -a.y;
             b.y = -b.y;
         }
+        if (DST == 3) {
+            constexpr float inv = 1.0f / (float)N;          // a power of two: exact
+            a = mk(a.x * inv, -a.y * inv);
+            b = mk(b.x * inv, -b.y * inv);
+        }
         if (DST == 2) {
             constexpr float inv = 1.0f / (float)N;          // a power of two: exact
             floatx4 q;
@@ -204,6 +218,67 @@ __device__ __forceinline__ void dd_pass16(int Ns, cfl* buf, const floatx4* __res
         }
     }
     if (DST != 2) __syncthreads();                         // the writes before the next pass reads
+}
+
+// Stokes parameters of the dedispersed block in LDS, integrated over t_int
+// consecutive samples; s points at period 0 of this block in the (c, b) row
+// of [T'][K].  With G = max(1, N / 256) samples per thread:
+//  - t_int < G: thread j takes samples j + 256 g (consecutive lanes on
+//    consecutive samples: conflict-free LDS reads, coalesced stores); a period
+//    spans t_int lanes and meets in an xor butterfly;
+//  - t_int >= G: thread j takes samples [G j, G j + G), read in an order
+//    rotated by j so that the lanes spread over the LDS banks; a longer period
+//    spans t_int / G lanes of a wave and meets in an xor butterfly
+//    (t_int <= 64 G).
+template <int K>
+__device__ __forceinline__ void dd_put(float* __restrict__ s, int period, const float (&v)[4]) {
+    if (K == 4) {
+        floatx4 o;
+        o[0] = v[0] + v[1];
+        o[1] = v[0] - v[1];
+        o[2] = 2.0f * v[2];
+        o[3] = 2.0f * v[3];
+        reinterpret_cast<floatx4*>(s)[period] = o;
+    } else {
+        s[period] = v[0] + v[1];
+    }
+}
+
+__device__ __forceinline__ void dd_terms(const cfl x, const cfl y, float (&v)[4]) {
+    v[0] += x.x * x.x + x.y * x.y;                          // |X|^2
+    v[1] += y.x * y.x + y.y * y.y;                          // |Y|^2
+    v[2] += x.x * y.x + x.y * y.y;                          // Re X conj(Y)
+    v[3] += x.y * y.x - x.x * y.y;                          // Im X conj(Y)
+}
+
+template <int N, int K>
+__device__ __forceinline__ void dd_stokes(const cfl* buf, float* __restrict__ s, int t_int) {
+    constexpr int G = N >= kDdThreads ? N / kDdThreads : 1;
+    const int j = threadIdx.x;
+    if (t_int < G) {
+        for (int g = 0; g < G; ++g) {
+            const int n = j + kDdThreads * g;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            dd_terms(buf[lds_index(n)], buf[lds_words<N>() + lds_index(n)], v);
+            for (int m = 1; m < t_int; m <<= 1)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], m, kWave);
+            if ((j & (t_int - 1)) == 0) dd_put<K>(s, n / t_int, v);
+        }
+        return;
+    }
+    const bool live = j * G < N;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int n = live ? j * G + ((g + j) & (G - 1)) : 0;
+        dd_terms(buf[lds_index(n)], buf[lds_words<N>() + lds_index(n)], v);
+    }
+    const int L = t_int / G;                                // lanes per period (a power of two <= 64)
+    for (int m = 1; m < L; m <<= 1)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], m, kWave);
+    if (live && (j & (L - 1)) == 0) dd_put<K>(s, j * G / t_int, v);
 }
 
 template <int N>
@@ -246,6 +321,69 @@ __global__ __launch_bounds__(kDdThreads) void dedisperse_kernel(const floatx4* _
     Ns = 1;
     for (int s = 0; s < P - 1; ++s, Ns *= 8) dd_pass<N, 1, 0>(Ns, buf, yb, hc, ob);
     dd_pass<N, 1, 2>(Ns, buf, yb, hc, ob);
+}
+
+// Dedispersion then Stokes and integration: s [C][B][T/t_int][K]
+template <int N, int K>
+__global__ __launch_bounds__(kDdThreads) void dedisperse_stokes_kernel(const floatx4* __restrict__ y,
+                                                                       const cfl* __restrict__ chirp,
+                                                                       float* __restrict__ s, int B, int T, int t_int) {
+    __shared__ __attribute__((aligned(16))) cfl buf[2 * lds_words<N>()];
+    const int nb = T / N;
+    const long wg = blockIdx.x;
+    const long cb = wg / nb;                                // c B + b
+    const int blk = (int)(wg - cb * nb);
+    const int c = (int)(cb / B);
+    const floatx4* yb = y + (size_t)cb * T + (size_t)blk * N;
+    const cfl* hc = chirp + (size_t)c * N;
+    float* sb = s + ((size_t)cb * (T / t_int) + (size_t)blk * (N / t_int)) * K;
+    if constexpr (N == 4096) {
+        dd_pass16<N, 0, 0>(1, buf, yb, hc, nullptr);
+        dd_pass16<N, 1, 0>(16, buf, yb, hc, nullptr);
+        dd_pass16<N, 1, 1>(256, buf, yb, hc, nullptr);
+        dd_pass16<N, 1, 0>(1, buf, yb, hc, nullptr);
+        dd_pass16<N, 1, 0>(16, buf, yb, hc, nullptr);
+        dd_pass16<N, 1, 3>(256, buf, yb, hc, nullptr);
+    } else {
+        constexpr int P = N == 8 ? 1 : N == 64 ? 2 : 3;
+        int Ns = 1;
+        if (P == 1) {
+            dd_pass<N, 0, 1>(Ns, buf, yb, hc, nullptr);
+        } else {
+            dd_pass<N, 0, 0>(Ns, buf, yb, hc, nullptr);
+            Ns *= 8;
+            for (int p = 1; p < P - 1; ++p, Ns *= 8) dd_pass<N, 1, 0>(Ns, buf, yb, hc, nullptr);
+            dd_pass<N, 1, 1>(Ns, buf, yb, hc, nullptr);
+        }
+        Ns = 1;
+        for (int p = 0; p < P - 1; ++p, Ns *= 8) dd_pass<N, 1, 0>(Ns, buf, yb, hc, nullptr);
+        dd_pass<N, 1, 3>(Ns, buf, yb, hc, nullptr);
+    }
+    dd_stokes<N, K>(buf, sb, t_int);                        // the last pass ended with a barrier
+}
+
+template <int N>
+static void launch_dd_stokes(dim3 g, const floatx4* yv, const cfl* hv, float* s, int B, int T, int product, int t_int,
+                             hipStream_t st) {
+    if (product == PR_IQUV)
+        hipLaunchKernelGGL((dedisperse_stokes_kernel<N, 4>), g, dim3(kDdThreads), 0, st, yv, hv, s, B, T, t_int);
+    else
+        hipLaunchKernelGGL((dedisperse_stokes_kernel<N, 1>), g, dim3(kDdThreads), 0, st, yv, hv, s, B, T, t_int);
+}
+
+hipError_t launch_dedisperse_stokes(const void* y, int C, int B, int T, int n_fft, const void* chirp, int product,
+                                    int t_int, float* s, hipStream_t st) {
+    const dim3 g((unsigned)((size_t)C * B * (T / n_fft)));
+    const floatx4* yv = static_cast<const floatx4*>(y);
+    const cfl* hv = static_cast<const cfl*>(chirp);
+    switch (n_fft) {
+        case 8: launch_dd_stokes<8>(g, yv, hv, s, B, T, product, t_int, st); break;
+        case 64: launch_dd_stokes<64>(g, yv, hv, s, B, T, product, t_int, st); break;
+        case 512: launch_dd_stokes<512>(g, yv, hv, s, B, T, product, t_int, st); break;
+        case 4096: launch_dd_stokes<4096>(g, yv, hv, s, B, T, product, t_int, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_dedisperse(const void* y, int C, int B, int T, int n_fft, const void* chirp, void* out,

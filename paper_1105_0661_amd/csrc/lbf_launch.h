@@ -68,5 +68,7 @@ hipError_t launch_channelize(const void* x, int xtype, int S, int NSB, int Tin, 
                              float* out, hipStream_t st);
 hipError_t launch_dedisperse(const void* y, int C, int B, int T, int n_fft, const void* chirp, void* out,
                              hipStream_t st);
+hipError_t launch_dedisperse_stokes(const void* y, int C, int B, int T, int n_fft, const void* chirp, int product,
+                                    int t_int, float* s, hipStream_t st);
 
 }  // namespace lbf

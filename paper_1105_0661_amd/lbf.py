@@ -102,6 +102,9 @@ _PROTOS = {
                                       ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_dedisperse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbf_dedisperse_stokes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "lbf_block_footprint": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.POINTER(BlockSizes)]),
     "lbf_check_addressing": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_uint64)]),
@@ -388,6 +391,18 @@ def dedisperse(y, chirp, n_fft: int = 4096, out=None, stream=None):
         out = torch.empty_like(y)
     _check(lib().lbf_dedisperse(_dev_ptr(y, "y"), C, B, T, n_fft, _dev_ptr(chirp, "chirp"), _dev_ptr(out, "out"),
                                 _stream(stream)))
+    return out
+
+
+def dedisperse_stokes(y, chirp, n_fft: int, product: int, t_int: int, out=None, stream=None):
+    """Dedispersion then Stokes and integration of voltages y [C][B][T][2][2]
+    f32 with chirp weights [C][n_fft][2] f32: [C][B][T/t_int][K] f32."""
+    torch = _torch()
+    C, B, T = y.shape[:3]
+    if out is None:
+        out = torch.empty((C, B, T // t_int, n_stokes(product)), dtype=torch.float32, device=y.device)
+    _check(lib().lbf_dedisperse_stokes(_dev_ptr(y, "y"), C, B, T, n_fft, _dev_ptr(chirp, "chirp"), product, t_int,
+                                       _dev_ptr(out, "out"), _stream(stream)))
     return out
 
 

@@ -181,3 +181,12 @@ def test_per_station_and_per_beam_rates():
     assert i1.output_bytes * 8 / seconds / 1e9 == pytest.approx(1.55, abs=0.01)
     full = lbf.block_footprint(64, nsb * nch, T, 1, lbf.CI16, lbf.F32, lbf.STOKES_I, 1)
     assert full.input_bytes * 8 / seconds / 1e9 == pytest.approx(198.4, abs=0.05)     # abstract: 198 Gb/s
+
+
+def test_dedisperse_stokes_argument_checks():
+    L = lbf.lib()
+    assert L.lbf_dedisperse_stokes(16, 1, 1, 4096, 4096, 16, lbf.STOKES_I, 3, 64, None) == lbf.E_INVAL   # t_int
+    assert L.lbf_dedisperse_stokes(16, 1, 1, 4096, 4096, 16, lbf.VOLTAGES, 1, 64, None) == lbf.E_INVAL  # product
+    assert L.lbf_dedisperse_stokes(16, 1, 1, 4000, 4096, 16, lbf.STOKES_I, 1, 64, None) == lbf.E_INVAL  # T
+    assert L.lbf_dedisperse_stokes(16, 1, 1, 64, 64, 16, lbf.STOKES_I, 128, 64, None) == lbf.E_INVAL    # t_int > n
+    assert L.lbf_dedisperse_stokes(None, 1, 1, 64, 64, 16, lbf.STOKES_I, 1, 64, None) == lbf.E_INVAL    # NULL

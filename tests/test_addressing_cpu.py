@@ -14,7 +14,7 @@ from paper_1105_0661_amd import lbf, synth
 pytestmark = pytest.mark.skipif(not os.path.exists(lbf.LIB_PATH), reason="liblbf.so not built")
 
 THREADS = max(1, min(8, os.cpu_count() or 1))
-X = {"ci8": lbf.CI8, "ci16": lbf.CI16}
+X = {"ci8": lbf.CI8, "ci16": lbf.CI16, "cf32": lbf.CF32}
 
 
 def _walk(S, C, T, B, xt, ct, prod, ti=1, fi=1, **kw):
@@ -32,7 +32,9 @@ TEST_SHAPES = [(13, 5, 112, 70, "ci16", lbf.VOLTAGES, 1), (1, 3, 32, 37, "ci8", 
                (40, 2, 64, 300, "ci8", lbf.STOKES_IQUV, 16), (40, 2, 64, 385, "ci8", lbf.VOLTAGES, 1),
                (40, 2, 64, 512, "ci16", lbf.STOKES_I, 16), (11, 10, 128, 40, "ci16", lbf.STOKES_I, 2),
                (20, 3, 1100, 140, "ci8", lbf.STOKES_IQUV, 4), (20, 3, 1100, 50, "ci16", lbf.VOLTAGES, 1),
-               (31, 5, 48, 1, "ci16", lbf.STOKES_I, 4), (64, 16, 768, 488, "ci8", lbf.STOKES_IQUV, 16)]
+               (31, 5, 48, 1, "ci16", lbf.STOKES_I, 4), (64, 16, 768, 488, "ci8", lbf.STOKES_IQUV, 16),
+               (12, 32, 64, 40, "cf32", lbf.STOKES_IQUV, 4), (13, 5, 112, 70, "cf32", lbf.VOLTAGES, 1),
+               (64, 256, 48, 128, "cf32", lbf.STOKES_IQUV, 16), (40, 6, 200, 150, "cf32", lbf.STOKES_I, 8)]
 
 
 @pytest.mark.parametrize("shape", TEST_SHAPES, ids=lambda s: "S%d_C%d_T%d_B%d_%s_K%d_t%d" % s)

@@ -114,3 +114,52 @@ def test_dedisperse_case_e_share_sampled():
         yc = y[c:c + 1, b:b + 1].cpu().numpy()
         want = orc.dedisperse(cplx(yc), cplx(h[c:c + 1].cpu().numpy()), n)
         assert relerr(cplx(out[c:c + 1, b:b + 1]), want) <= TOL, (c, b)
+
+
+# (C, B, T, n_fft, product, t_int): periods inside a thread (t_int <= n_fft / 256),
+# across lanes (up to 64 lanes: t_int 1024 at 4096), the small transforms
+# with fewer threads than the block's work group, both products
+STOKES_CASES = [(2, 3, 8192, 4096, lbf.STOKES_IQUV, 16), (1, 2, 4096, 4096, lbf.STOKES_I, 1),
+                (2, 2, 8192, 4096, lbf.STOKES_IQUV, 1024), (2, 2, 4096, 4096, lbf.STOKES_IQUV, 64),
+                (3, 2, 1024, 512, lbf.STOKES_IQUV, 2), (2, 2, 1024, 512, lbf.STOKES_I, 128),
+                (3, 2, 192, 64, lbf.STOKES_IQUV, 4), (2, 1, 128, 64, lbf.STOKES_I, 64),
+                (3, 2, 24, 8, lbf.STOKES_IQUV, 8), (2, 2, 16, 8, lbf.STOKES_I, 1)]
+
+
+@pytest.mark.parametrize("case", STOKES_CASES, ids=lambda c: "C%d_B%d_T%d_n%d_K%d_t%d" % c)
+def test_dedisperse_stokes_matches_oracle_and_the_two_step_chain(case):
+    """Dedispersion then Stokes and integration in one kernel, against the
+    oracle's dedispersion followed by its Stokes and integration steps, and
+    against lbf_dedisperse + lbf_stokes on the GPU."""
+    torch = _torch()
+    C, B, T, n, prod, ti = case
+    K = lbf.n_stokes(prod)
+    y, h = _voltages(C, B, T, 7 * n + ti), _chirp(C, n, n + 1)
+    flush("dedisperse+Stokes %s" % (case,))
+    yd, hd = to_dev(y), to_dev(h)
+    s = lbf.dedisperse_stokes(yd, hd, n, prod, ti)                         # [C][B][T'][K]
+    two = lbf.stokes(lbf.dedisperse(yd, hd, n), prod, ti, 1)
+    torch.cuda.synchronize()
+    ref = orc.integrate(orc.stokes(_oracle(y, h, n)), K, ti, 1)            # [C][B][T'][K]
+    got = s.cpu().numpy()
+    assert got.shape == ref.shape
+    for k in range(K):
+        # Q, U and V of independent Gaussian polarisations average out: measure
+        # every parameter against Stokes I of the same (channel, beam)
+        for c in range(C):
+            for b in range(B):
+                den = np.linalg.norm(ref[c, b, :, 0])
+                assert np.linalg.norm(got[c, b, :, k] - ref[c, b, :, k]) <= TOL * den, (k, c, b)
+    assert np.linalg.norm(got - two.cpu().numpy()) <= 1e-6 * np.linalg.norm(got[..., 0])
+
+
+def test_dedisperse_stokes_rejects_unsupported_integrations():
+    torch = _torch()
+    y = torch.zeros((1, 1, 4096, 2, 2), device="cuda:0")
+    h = torch.zeros((1, 4096, 2), device="cuda:0")
+    for ti in (3, 2048, 8192):
+        with pytest.raises(lbf.LbfError) as ei:
+            lbf.dedisperse_stokes(y, h, 4096, lbf.STOKES_IQUV, ti)
+        assert ei.value.code == lbf.E_INVAL
+    with pytest.raises(lbf.LbfError):
+        lbf.dedisperse_stokes(y[:, :, :512].contiguous(), h[:, :512].contiguous(), 512, lbf.STOKES_I, 256)

@@ -49,11 +49,12 @@ def _samples_exact(x, ctype):
     return int(np.abs(x).max()) <= lim
 
 
-def _check_stokes(out, ref, tol, label, blk=None, ctype=None, t_int=1, f_int=1, chans=None):
+def _check_stokes(out, ref, tol, label, blk=None, ctype=None, t_int=1, f_int=1, chans=None, scale="own"):
     """Norm-wise per parameter; element-wise against the rounding bound when
     the block is given (chans: the block's channels the output holds), and
-    against 10 tol rms for FP32 / FP16 operands."""
-    check_stokes(out, ref, tol, label, elem_factor=10.0 if ctype != lbf.BF16 else float("inf"))
+    against 10 tol rms for FP32 / FP16 operands.  scale="I": Q, U and V
+    against Stokes I (see check_stokes)."""
+    check_stokes(out, ref, tol, label, scale=scale, elem_factor=10.0 if ctype != lbf.BF16 else float("inf"))
     if blk is None:
         return
     x = blk.x if chans is None else np.ascontiguousarray(blk.x[:, chans])
@@ -164,6 +165,28 @@ def test_fast_path_station_and_sample_edges(ctype, S, T):
     ref = orc.beamform(blk.x, orc.block_weights(blk))
     _check_volt(cplx(y), ref, TOL[ctype], "fast edges voltages")
     _check_stokes(s.cpu().numpy(), _oracle_stokes(blk, 4, ti, 1), TOL[ctype], "fast edges", blk, ctype, ti)
+
+
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
+@pytest.mark.parametrize("S,B,T,t_int", [(40, 150, 200, 8), (64, 300, 96, 16), (7, 20, 45, 1)])
+def test_complex_float_input_on_the_fast_path(ctype, S, B, T, t_int):
+    # channelised (complex f32) station samples through the fast workers: one
+    # 16-byte load per sample, rounded to the operand type in the loaders.
+    # BF16 rounds the (non-integer) samples as well as the weights to 8
+    # significant bits: there Q, U and V (noise-like, with norms below that
+    # of I) are measured against Stokes I; every element still meets its
+    # rounding bound
+    torch = _torch()
+    blk = synth.make_block(S, B, 2, 3, T, "cf32", 30.0, tag=(1105, 661, 67))
+    flush("cf32 fast %s S=%d B=%d T=%d" % (CT_NAMES[ctype], S, B, T))
+    x, w = to_dev(blk.x), _weights(blk, ctype)
+    y = lbf.beamform(x, w, lbf.VOLTAGES)
+    ti = t_int if T % t_int == 0 else 1
+    s = lbf.beamform(x, w, lbf.STOKES_IQUV, ti, 1)
+    torch.cuda.synchronize()
+    _check_volt(cplx(y), orc.beamform(blk.x, orc.block_weights(blk)), TOL[ctype], "cf32 voltages")
+    _check_stokes(s.cpu().numpy(), _oracle_stokes(blk, 4, ti, 1), TOL[ctype], "cf32 Stokes", blk, ctype, ti,
+                  scale="I" if ctype == lbf.BF16 else "own")
 
 
 @pytest.mark.parametrize("ctype", [lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
