@@ -155,10 +155,13 @@ def unfused(lbf, torch, x, geo, nch, steps, warmup):
             "rel_err_vs_fused": err}
 
 
-def incoherent(lbf, torch, x, steps, warmup, mp):
+def incoherent(lbf, torch, x, steps, warmup, mp, geo=None):
     """The incoherent beam (sum over stations of the station powers) of the
     whole one-second block, Stokes IQUV integrated x16: an HBM-bound read of
-    every sample once.  HIP events on the current stream around each launch."""
+    every sample once.  HIP events on the current stream around each launch.
+    With the block's geometry, also both products from one read of the
+    samples (lbf_beamform_incoherent, FP16 MFMA) against lbf_beamform then
+    lbf_incoherent."""
     S, C, T = x.shape[:3]
     n = warmup + steps
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n)]
@@ -177,6 +180,30 @@ def incoherent(lbf, torch, x, steps, warmup, mp):
          "frac": gbps / PEAK["hbm_GBps"]}
     if mp:
         r["frac_of_measured_hbm"] = gbps / max(mp["hbm_GBps"], mp["hbm_read_GBps"])
+    if geo is not None:
+        pos, dirs, freq, ref = geo
+        B = dirs.shape[0]
+        w = lbf.compute_weights(pos, dirs, freq, lbf.F16, ref_dir=ref)
+        bf = torch.empty((B, 4, T // 16, C), dtype=torch.float32, device=x.device)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n)]
+        for i in range(n):
+            ev[i][0].record()
+            lbf.beamform_incoherent(x, w, lbf.STOKES_IQUV, 16, 1, out=bf, inc=out)
+            ev[i][1].record()
+            lbf.beamform(x, w, lbf.STOKES_IQUV, 16, 1, out=bf)
+            ev[i][2].record()
+            lbf.incoherent(x, lbf.STOKES_IQUV, 16, 1, out=out)
+            ev[i][3].record()
+        torch.cuda.synchronize()
+
+        def span(a, b):
+            return float(np.mean([ev[i][a].elapsed_time(ev[i][b]) for i in range(warmup, n)]))
+
+        r["with_beams"] = {"workload": "128 tied-array beams (FP16 MFMA, Stokes IQUV x16, final order) and the "
+                                       "incoherent beam of the one-second block",
+                           "one_read_ms": span(0, 1), "two_reads_ms": span(1, 3),
+                           "beamform_ms": span(1, 2), "incoherent_ms": span(2, 3)}
+        del w, bf
     return r
 
 
@@ -694,7 +721,7 @@ def main():
     if not a.no_extra and not only:
         unfused_res = unfused(lbf, torch, x, geo, 1024, max(3, a.steps // 4), 1)
         log("unfused chain: %s" % unfused_res)
-        inc_res = incoherent(lbf, torch, x, max(5, a.steps // 2), a.warmup, mp)
+        inc_res = incoherent(lbf, torch, x, max(5, a.steps // 2), a.warmup, mp, geo)
         log("incoherent beam: %s" % inc_res)
         dd_res = dedispersion(lbf, torch, dev, max(5, a.steps // 2), a.warmup, mp)
         log("dedispersion: %s" % dd_res)

@@ -129,6 +129,23 @@ typedef struct {
 int lbf_beamform(const lbf_block* blk, void* stream);
 
 /*
+ * lbf_beamform together with the incoherent beam of the same block (Section
+ * 3: the station powers summed unweighted, a product formed beside the
+ * tied-array beams from the same station data), d_inc laid out as
+ * lbf_incoherent's output, f32 [K][T'][C'].  Blocks of at most 128 beams on
+ * the FP16/BF16 fast worker (HBM-bound) read the station samples once: the
+ * work items of their beam group form the incoherent beam from the sample
+ * tile they stage, in FP32 from the operand-type samples (equal to
+ * lbf_incoherent up to FP32 rounding when the operand type holds the samples
+ * exactly: complex int8, int16 up to 2048 in FP16 and up to 256 in BF16).
+ * Other blocks, whose contraction is bound by MFMA work, run lbf_beamform and
+ * then lbf_incoherent.  d_out equals lbf_beamform's output bit for bit.
+ * Errors: as lbf_beamform; LBF_E_INVAL for voltages, a NULL d_inc or one that
+ * overlaps the samples or the output.
+ */
+int lbf_beamform_incoherent(const lbf_block* blk, float* d_inc, void* stream);
+
+/*
  * lbf_beamform for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same result bit for bit, but no call to hipMalloc, hipFree or any other

@@ -84,6 +84,7 @@ lbf::BlockDesc to_desc(const lbf_block* b) {
     d.ld_row = b->B * (b->product == LBF_STOKES_IQUV ? 4 : 1);
     d.c0 = 0;
     d.nc = b->C;
+    d.inc = nullptr;
     return d;
 }
 
@@ -190,6 +191,35 @@ int lbf_compute_weights(const double* d_station_xyz, int S, const double* d_beam
 
 int lbf_beamform(const lbf_block* blk, void* stream) {
     return lbf::run_block(blk, nullptr, 0, stream, "lbf_beamform");
+}
+
+int lbf_beamform_incoherent(const lbf_block* blk, float* d_inc, void* stream) {
+    int rc = check_block(blk, "lbf_beamform_incoherent");
+    if (rc) return rc;
+    if (blk->product == LBF_VOLTAGES)
+        return fail(LBF_E_INVAL, "lbf_beamform_incoherent: the incoherent beam comes with a Stokes product");
+    if (!d_inc) return fail(LBF_E_INVAL, "lbf_beamform_incoherent: NULL device pointer");
+    const size_t inc_bytes = (size_t)blk->product * (blk->T / blk->t_int) * (blk->C / blk->f_int) * sizeof(float);
+    const size_t out_bytes = (size_t)blk->B * inc_bytes;
+    const size_t x_bytes = (size_t)blk->S * blk->C * blk->T * 2 * bytes_per_complex(blk->xtype);
+    const char* ic = (const char*)d_inc;
+    const char* o = (const char*)blk->d_out;
+    const char* x = (const char*)blk->d_x;
+    if ((ic < o + out_bytes && o < ic + inc_bytes) || (ic < x + x_bytes && x < ic + inc_bytes))
+        return fail(LBF_E_INVAL, "lbf_beamform_incoherent: the incoherent beam overlaps the samples or the output");
+    lbf::BlockDesc d = to_desc(blk);
+    hipError_t e;
+    if (lbf::fuses_incoherent(d)) {
+        d.inc = d_inc;                                    // formed by the contraction's first beam group
+        e = lbf::launch_beamform(d, (hipStream_t)stream);
+    } else {
+        e = lbf::launch_beamform(d, (hipStream_t)stream);
+        if (e == hipSuccess)
+            e = lbf::launch_incoherent(blk->d_x, blk->xtype, blk->S, blk->C, blk->T, blk->product, blk->t_int,
+                                       blk->f_int, d_inc, (hipStream_t)stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "lbf_beamform_incoherent");
+    return ok();
 }
 
 int lbf_beamform_noalloc(const lbf_block* blk, void* stream) {

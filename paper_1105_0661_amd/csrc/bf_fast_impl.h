@@ -13,11 +13,12 @@ __global__ __launch_bounds__(kThreadsH) void bf_f32_fast_kernel(BlockDesc d, int
     item_f32_fast<XT, PR, TI>(d, xcd_remap(blockIdx.x, nitems), nbg, pl);
 }
 
-// 8 waves, two per SIMD; LDS: NS streams x 2 buffers of one A tile
-template <int XT, int CT, int PR, int TI, int NK, int NS>
+// 8 waves, two per SIMD; LDS: NS streams x 2 buffers of one A tile (and the
+// incoherent beam's partial sums in the INC form)
+template <int XT, int CT, int PR, int TI, int NK, int NS, bool INC>
 __global__ __launch_bounds__(kThreadsH) void bf_h_fast_kernel(BlockDesc d, int nbg, int nitems) {
-    __shared__ __attribute__((aligned(16))) uint32_t at[NS * 2 * kATileWords];
-    item_h_fast<XT, CT, PR, TI, NK, NS>(d, xcd_remap(blockIdx.x, nitems), nbg, at);
+    __shared__ __attribute__((aligned(16))) uint32_t at[NS * 2 * kATileWords + (INC ? kIncLdsFloats : 0)];
+    item_h_fast<XT, CT, PR, TI, NK, NS, INC>(d, xcd_remap(blockIdx.x, nitems), nbg, at);
 }
 
 // launch one instantiation; PR/TI/NK chosen from the block by the callers
@@ -46,16 +47,29 @@ inline hipError_t launch_f32_xt(const BlockDesc& d, int nbg, int n, hipStream_t 
     return launch_f32_pr<XT, PR_IQUV>(d, nbg, n, st);
 }
 
-template <int XT, int CT, int PR, int TI, int NS>
-inline void launch_h_ns(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+template <int XT, int CT, int PR, int TI, int NS, bool INC>
+inline void launch_h_nsi(const BlockDesc& d, int nbg, int n, hipStream_t st) {
     const dim3 g(n), b(kThreadsH);
     switch (fast_h_ksteps(d.S)) {
-        case 4: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4, NS>), g, b, 0, st, d, nbg, n); break;
-        case 5: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 5, NS>), g, b, 0, st, d, nbg, n); break;
-        case 6: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 6, NS>), g, b, 0, st, d, nbg, n); break;
-        case 7: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 7, NS>), g, b, 0, st, d, nbg, n); break;
-        default: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8, NS>), g, b, 0, st, d, nbg, n); break;
+        case 4: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 4, NS, INC>), g, b, 0, st, d, nbg, n); break;
+        case 5: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 5, NS, INC>), g, b, 0, st, d, nbg, n); break;
+        case 6: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 6, NS, INC>), g, b, 0, st, d, nbg, n); break;
+        case 7: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 7, NS, INC>), g, b, 0, st, d, nbg, n); break;
+        default: hipLaunchKernelGGL((bf_h_fast_kernel<XT, CT, PR, TI, 8, NS, INC>), g, b, 0, st, d, nbg, n); break;
     }
+}
+
+// the INC form (incoherent beam beside the Stokes products) only for Stokes
+// with two sample streams (fuses_incoherent)
+template <int XT, int CT, int PR, int TI, int NS>
+inline void launch_h_ns(const BlockDesc& d, int nbg, int n, hipStream_t st) {
+    if constexpr (PR != PR_VOLT && NS == 2) {
+        if (d.inc != nullptr) {
+            launch_h_nsi<XT, CT, PR, TI, NS, true>(d, nbg, n, st);
+            return;
+        }
+    }
+    launch_h_nsi<XT, CT, PR, TI, NS, false>(d, nbg, n, st);
 }
 
 template <int XT, int CT, int PR, int TI>

@@ -93,6 +93,10 @@ hipError_t staging_alloc(void** p, size_t bytes, hipStream_t st) {
 // 32 floats, and a tiled transpose.
 bool needs_staging(const BlockDesc& d) { return fast_path(d) && d.product != PR_VOLT && d.order == 0; }
 
+bool fuses_incoherent(const BlockDesc& d) {
+    return fast_path(d) && d.ctype != CT_F32 && d.product != PR_VOLT && fast_h_streams(d) == 2;
+}
+
 size_t staging_channel_bytes(const BlockDesc& d) {
     const int K = d.product == PR_IQUV ? 4 : 1;
     return (size_t)(d.T / d.t_int) * staging_ld(d.B, K) * sizeof(float);

@@ -268,7 +268,33 @@ template <> struct Chunk<XT_CF32, CT_BF16> {
     }
 };
 
-template <int XT, int CT, int PR, int TI, int NK, int NS>
+// FP32 values of one packed 16-bit complex operand word (re low, im high)
+template <int CT> LBF_INLINE void unpack2(uint32_t w, float& re, float& im);
+template <> LBF_INLINE void unpack2<CT_F16>(uint32_t w, float& re, float& im) {
+    const halfx2 v = __builtin_bit_cast(halfx2, w);
+    re = (float)v[0];
+    im = (float)v[1];
+}
+template <> LBF_INLINE void unpack2<CT_BF16>(uint32_t w, float& re, float& im) {
+    re = __uint_as_float(w << 16);
+    im = __uint_as_float(w & 0xffff0000u);
+}
+
+// Floats of LDS the incoherent-beam form of item_h_fast adds: per step
+// parity, sample stream, wave of the stream and tile sample, four sums.
+constexpr int kIncLdsFloats = 2 * 8 * kTile * 4;
+
+// The worker's INC form also forms the incoherent beam (Section 3: the
+// stations' powers summed, unweighted) of its channel and samples from the
+// sample tile staged in LDS, so that one read of the station data gives both
+// products.  Only the items of the first beam group do this, one per
+// (channel, sample segment).  Each wave of a stream sums |X|^2, |Y|^2 and
+// X conj(Y) over its share of the stations (lanes: tile sample; lane halves:
+// halves of the share; products of 16-bit values are exact in FP32), the
+// shares meet in LDS and are summed in wave order by the stream's first wave
+// after the step's barrier, which then integrates t_int consecutive samples
+// in an xor butterfly and stores I (Q, U, V) into inc [K][T'][C].
+template <int XT, int CT, int PR, int TI, int NK, int NS, bool INC = false>
 LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at) {
     typedef typename MfmaH<CT>::vec V;
     constexpr int BYTES = sample_bytes(XT);
@@ -355,6 +381,61 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     // (complex int16 with two streams, more than two chunks per thread)
     constexpr bool PIPE = !(XT == XT_CI16 && NS == 2) && CPT <= 2;
     constexpr int NOUT = PR == PR_VOLT ? 1 : 16 / TI;
+
+    // incoherent beam of the item's tiles (INC form, first beam group only)
+    constexpr int SPW = 8 * NK / NBT;                      // stations per wave of a stream
+    constexpr int SPH = (SPW + 1) / 2;                     // of which lane half 0 takes SPH, half 1 the rest
+    float* incl = reinterpret_cast<float*>(at + NS * 2 * kATileWords);
+    const bool inc_on = INC && PR != PR_VOLT && bg == 0 && d.b0 == 0;
+    auto inc_partial = [&](int k) {                        // the tile of step k: this wave's share
+        const uint32_t* tb = at + (sigma * 2 + (k & 1)) * kATileWords;
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < SPH; ++i) {
+            if (h * SPH + i >= SPW) break;                 // an odd share: half 1 has one station less
+            const int s = bt * SPW + h * SPH + i;
+            float xr, xi, yr, yi;
+            unpack2<CT>(tb[a_word(r, 0, s)], xr, xi);
+            unpack2<CT>(tb[a_word(r, 1, s)], yr, yi);
+            v[0] = __builtin_fmaf(xi, xi, __builtin_fmaf(xr, xr, v[0]));
+            v[1] = __builtin_fmaf(yi, yi, __builtin_fmaf(yr, yr, v[1]));
+            v[2] = __builtin_fmaf(xi, yi, __builtin_fmaf(xr, yr, v[2]));
+            v[3] = __builtin_fmaf(-xr, yi, __builtin_fmaf(xi, yr, v[3]));
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], 32, kWave);   // the two lane halves
+        if (h == 0) {
+            floatx4 o;
+            o[0] = v[0];
+            o[1] = v[1];
+            o[2] = v[2];
+            o[3] = v[3];
+            *reinterpret_cast<floatx4*>(incl + ((((k & 1) * NS + sigma) * NBT + bt) * kTile + r) * 4) = o;
+        }
+    };
+    auto inc_finish = [&](int k) {                         // after the barrier: step k's tile, first wave of the stream
+        const int tile = tile_lo + sigma + NS * k;
+        if (bt != 0 || k < 0 || tile >= tile_lo + ntiles) return;
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int w = 0; w < NBT; ++w) {
+            const floatx4 p = *reinterpret_cast<const floatx4*>(incl + ((((k & 1) * NS + sigma) * NBT + w) * kTile + r) * 4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] += p[q];
+        }
+#pragma unroll
+        for (int m = 1; m < TI; m <<= 1)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], m, kWave);
+        float o[4];
+        stokes_from_sums<PR_IQUV>(v, o);                   // I, Q, U, V from |X|^2, |Y|^2, X conj(Y)
+        const int tq = (tile * kTile + r) / TI;
+        if (h == 0 && (r & (TI - 1)) == 0 && tq < T2) {
+            constexpr int K = PR == PR_IQUV ? 4 : 1;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) d.inc[((size_t)kk * T2 + tq) * d.C + c] = o[kk];
+        }
+    };
     auto step = [&](int k, floatx16 (&acc)[4], const floatx16 (&prev)[4]) {
         load_chunks(k + 1);
         int rowx = (sigma * 2 + (k & 1)) * kATileWords + 2 * trow * kARow;
@@ -403,6 +484,10 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
 #pragma unroll
                 for (int i = 0; i < CPT; ++i)
                     if (i % 2 == kk - (NK - 2)) store_chunk(k + 1, i);
+            }
+            if (INC && inc_on) {
+                if (kk == 0) inc_partial(k);
+                if (kk == 1) inc_finish(k - 1);
             }
             // keep this slice's sums here (left alone, the compiler sinks the
             // whole epilogue below the last MFMA)
@@ -461,6 +546,10 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
                 acc[2] = MfmaH<CT>::mfma(b, br, kk == 0 ? zero16() : acc[2]);
                 acc[3] = MfmaH<CT>::mfma(b, bi, kk == 0 ? zero16() : acc[3]);
             }
+            if (INC && inc_on) {
+                inc_finish(k - 1);
+                inc_partial(k);
+            }
             final_epilogue(acc, k);
 #pragma unroll
             for (int i = 0; i < CPT; ++i) store_chunk_from(k + 1, i, next);
@@ -472,6 +561,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
             plain_step(k + 1, rr[1], rr[0]);
         }
         if (k < nsteps) plain_step(k, rr[0], rr[1]);
+        if (INC && inc_on) inc_finish(nsteps - 1);
         return;
     }
     floatx16 acc0[4], acc1[4];
@@ -488,6 +578,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     } else {
         final_epilogue(acc1, k - 1);
     }
+    if (INC && inc_on) inc_finish(nsteps - 1);
 }
 
 // ===========================================================================

@@ -35,6 +35,7 @@ struct BlockDesc {
     int ld_row;         // Stokes order 1: floats per [C'][T'] row of [B][K] values (>= B*K)
     int c0, nc;         // fast workers: channels [c0, c0 + nc) (0, C for a whole block); their output
                         // holds channel c at index c - c0
+    float* inc;         // FP16/BF16 fast worker, Stokes: also the incoherent beam [K][T'][C], or NULL
 };
 
 // ---------------------------------------------------------------------------

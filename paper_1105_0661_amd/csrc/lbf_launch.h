@@ -19,6 +19,11 @@ hipError_t launch_beamform(const BlockDesc& d, hipStream_t st);
 // caller-provided buffer of cap bytes (passes of staging_chunk(d, cap)
 // channels; hipErrorInvalidValue if not one channel fits).
 bool needs_staging(const BlockDesc& d);
+// The block's incoherent beam is formed by its contraction: the fast FP16/BF16
+// worker with two sample streams (at most 128 beams, HBM-bound).  With more
+// beams that worker is bound by MFMA and VALU work, and a separate read of
+// the samples costs less than the extra work in every item (measured).
+bool fuses_incoherent(const BlockDesc& d);
 size_t staging_channel_bytes(const BlockDesc& d);
 int staging_chunk(const BlockDesc& d, size_t cap);
 hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, hipStream_t st);

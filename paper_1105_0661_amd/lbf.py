@@ -86,6 +86,7 @@ _PROTOS = {
     "lbf_beamform": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
     "lbf_beamform_channel_major": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
     "lbf_beamform_noalloc": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p]),
+    "lbf_beamform_incoherent": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_beam_major": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "lbf_beamform_batch": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.c_void_p]),
@@ -249,6 +250,22 @@ def beamform(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, strea
     blk = make_block(x, w, product, t_int, f_int, out)
     _check(lib().lbf_beamform(ctypes.byref(blk), _stream(stream)))
     return out
+
+
+def beamform_incoherent(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, inc=None, stream=None):
+    """``beamform`` and the incoherent beam [K][T'][C'] of the same block
+    (one read of the samples on the FP16/BF16 fast path): (out, inc)."""
+    torch = _torch()
+    S, C, T = x.shape[0], x.shape[1], x.shape[2]
+    B = w.shape[1]
+    if out is None:
+        out = torch.empty(output_shape(product, S, C, T, B, t_int, f_int), dtype=torch.float32, device=x.device)
+    if inc is None:
+        K = n_stokes(product) if product in (STOKES_I, STOKES_IQUV) else 1   # voltages: refused by the library
+        inc = torch.empty((K, T // t_int, C // f_int), dtype=torch.float32, device=x.device)
+    blk = make_block(x, w, product, t_int, f_int, out)
+    _check(lib().lbf_beamform_incoherent(ctypes.byref(blk), _dev_ptr(inc, "inc"), _stream(stream)))
+    return out, inc
 
 
 def beamform_noalloc(x, w, product: int, t_int: int = 1, f_int: int = 1, out=None, stream=None):

@@ -368,6 +368,64 @@ def test_incoherent_beam_matches_oracle(case):
         check_close(got[k].T[None], ref[..., k][None], 1e-5, "incoherent %s" % "IQUV"[k])
 
 
+# (S, B, nsb, nch, T, xtype, ctype, product, t_int): blocks of at most 128
+# beams on the FP16/BF16 fast worker form the incoherent beam in the
+# contraction -- every K-step count, ragged T, several time segments, every
+# fused t_int, both input integer types; then blocks that run the two kernels
+# (more beams, complex f32, FP32 operands, 70 stations)
+INC_CASES = [(11, 40, 2, 5, 128, "ci16", lbf.F16, lbf.STOKES_IQUV, 16),
+             (37, 100, 1, 4, 96, "ci8", lbf.F16, lbf.STOKES_I, 4),
+             (53, 120, 1, 3, 80, "ci8", lbf.BF16, lbf.STOKES_IQUV, 8),
+             (64, 128, 1, 3, 64, "ci8", lbf.F16, lbf.STOKES_IQUV, 16),
+             (29, 20, 2, 3, 1100, "ci16", lbf.BF16, lbf.STOKES_I, 2),
+             (40, 90, 1, 4, 208, "ci8", lbf.F16, lbf.STOKES_IQUV, 1),
+             (45, 70, 1, 2, 300, "ci16", lbf.F16, lbf.STOKES_IQUV, 4),
+             (64, 488, 1, 3, 64, "ci8", lbf.F16, lbf.STOKES_IQUV, 16),
+             (25, 60, 1, 3, 96, "cf32", lbf.F16, lbf.STOKES_IQUV, 16),
+             (12, 30, 1, 4, 64, "ci16", lbf.F32, lbf.STOKES_IQUV, 16),
+             (70, 40, 1, 4, 64, "ci8", lbf.F16, lbf.STOKES_IQUV, 16)]
+
+
+@pytest.mark.parametrize("case", INC_CASES, ids=lambda c: "S%d_B%d_C%d_T%d_%s_%s_K%d_t%d" % (
+    c[0], c[1], c[2] * c[3], c[4], c[5], CT_NAMES[c[6]], c[7], c[8]))
+def test_beamform_with_incoherent_beam(case):
+    """The tied-array beams and the incoherent beam from one call: the beams
+    bitwise equal to lbf_beamform, the incoherent beam against the oracle
+    (1e-5; 3e-3 for complex f32 samples rounded to the operand type) and
+    against lbf_incoherent."""
+    torch = _torch()
+    S, B, nsb, nch, T, xt, ct, prod, ti = case
+    blk = synth.make_block(S, B, nsb, nch, T, xt, 16.0 if xt == "ci8" else 40.0, tag=(1105, 661, 68))
+    flush("beamform + incoherent %s" % (case,))
+    x, w = to_dev(blk.x), _weights(blk, ct)
+    out, inc = lbf.beamform_incoherent(x, w, prod, ti, 1)
+    alone = lbf.beamform(x, w, prod, ti, 1)
+    inc2 = lbf.incoherent(x, prod, ti, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(out, alone)
+    K = lbf.n_stokes(prod)
+    ref = orc.incoherent(blk.x, K, ti, 1)                       # [C'][T'][K]
+    got = inc.cpu().numpy()                                      # [K][T'][C']
+    tol = 3e-3 if xt == "cf32" and ct != lbf.F32 else 1e-5
+    for k in range(K):
+        check_close(got[k].T[None], ref[..., k][None], tol, "incoherent %s" % "IQUV"[k])
+    if tol == 1e-5:
+        check_close(got[None], inc2.cpu().numpy()[None], 1e-6, "fused vs lbf_incoherent")
+
+
+def test_beamform_incoherent_rejects_voltages_and_overlap():
+    torch = _torch()
+    blk = synth.make_block(8, 10, 1, 2, 64, "ci8", 16.0, tag=(1105, 661, 69))
+    x, w = to_dev(blk.x), _weights(blk, lbf.F16)
+    with pytest.raises(lbf.LbfError) as ei:
+        lbf.beamform_incoherent(x, w, lbf.VOLTAGES)
+    assert ei.value.code == lbf.E_INVAL
+    out = torch.empty((10, 4, 4, 2), device="cuda:0")
+    with pytest.raises(lbf.LbfError) as ei:
+        lbf.beamform_incoherent(x, w, lbf.STOKES_IQUV, 16, 1, out=out, inc=out[0])
+    assert ei.value.code == lbf.E_INVAL
+
+
 # --------------------------------------------------------------------------
 # batches: persistent launches per worker variant == separate launches, bit for bit
 # --------------------------------------------------------------------------
