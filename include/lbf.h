@@ -347,6 +347,19 @@ int lbf_probe(int kind, int iters, const void* d_src, void* d_dst, uint64_t byte
 int lbf_check_addressing(const lbf_block* blk, int channel_major, uint64_t staging_cap, int threads,
                          uint64_t* accesses);
 
+/*
+ * Tuning hook (not part of the beam former): the tile shape of the FP16/BF16
+ * fast worker's work items -- 1, 2 or 4 sample streams, i.e. items of 256,
+ * 128 or 64 beams -- comes from a table measured per input type, station
+ * count and beam count (tiles.json, compiled into the library).  streams = 1,
+ * 2 or 4 forces that shape for every later call in this process (complex f32
+ * samples keep 1); 0 restores the table.  For the sweep that measures the
+ * table; it changes only speed, never results.  Not synchronised with calls
+ * running on other threads.
+ * Errors: LBF_E_INVAL for other values.
+ */
+int lbf_set_tile_streams(int streams);
+
 /* Bytes of each operand of a block (host arithmetic, no device access). */
 typedef struct {
     uint64_t input_bytes, weight_bytes, output_bytes;

@@ -45,6 +45,8 @@ def _compile(src: str) -> str:
 
 
 def build(verbose: bool = False) -> str:
+    from paper_1105_0661_amd import gen_tile_table
+    gen_tile_table.generate()                  # csrc/tile_table.h from the measured tiles.json
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:

@@ -69,14 +69,18 @@ LBF_HD uint32_t weight_off(int beam, int S, int s, int bytes) { return ((uint32_
 // The FP16/BF16 worker's sample loaders: chunk j (thread tid + 512 i) of step
 // k covers stream sg, station s and samples SPC q .. SPC q + SPC - 1 of tile
 // `tile` (the stream's tile of that step, or its last tile once it has run
-// out).
+// out).  Chunks past the step's ns tiles (a step of fewer chunks than
+// threads) are not live: they load nothing (offset kNoStore) and are not
+// staged.
 struct Chunk16 {
     int s, q, tile;
+    bool live;
 };
 
 LBF_HD Chunk16 h_chunk(int j, int k, int ns, int cptile, int cps, int tile_lo, int ntiles) {
     const int sg = j / cptile, jt = j % cptile;
     Chunk16 ch;
+    ch.live = sg < ns;
     ch.s = jt / cps;
     ch.q = jt % cps;
     const int i = sg + ns * k;

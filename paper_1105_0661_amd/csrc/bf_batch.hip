@@ -29,12 +29,13 @@ __host__ __device__ inline bool batch_fast(const BlockDesc& d) {
     return fast_path(d) && d.t_int == 16 && d.xtype != XT_CF32;
 }
 
-// variant index of a fast block: ((xtype, product), K-steps 4..8, streams)
-constexpr int kBatchVariants = 2 * 2 * 5 * 2;
+// variant index of a fast block: ((xtype, product), K-steps 4..8, streams 1, 2, 4)
+constexpr int kBatchVariants = 2 * 2 * 5 * 3;
 inline int batch_variant(const BlockDesc& d) {
     const int ik = fast_h_ksteps(d.S) - 4;
     const int xp = (d.xtype == XT_CI8 ? 0 : 2) + (d.product == PR_I ? 0 : 1);
-    return (xp * 5 + ik) * 2 + (fast_h_streams(d) - 1);
+    const int ns = fast_h_streams(d);
+    return (xp * 5 + ik) * 3 + (ns == 1 ? 0 : ns == 2 ? 1 : 2);
 }
 
 template <int XT, int CT, int PR, int NK, int NS>
@@ -78,25 +79,29 @@ hipError_t launch_batch_k(const BatchArgs& a, int* counter, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int XT, int CT, int PR, int NK>
+hipError_t launch_batch_nk(int v, const BatchArgs& a, int* counter, hipStream_t st) {
+    switch (v % 3) {
+        case 0: return launch_batch_k<XT, CT, PR, NK, 1>(a, counter, st);
+        case 1: return launch_batch_k<XT, CT, PR, NK, 2>(a, counter, st);
+        default: return launch_batch_k<XT, CT, PR, NK, 4>(a, counter, st);
+    }
+}
+
 template <int XT, int CT, int PR>
 hipError_t launch_batch_pr(int v, const BatchArgs& a, int* counter, hipStream_t st) {
-    switch (v % 10) {
-        case 0: return launch_batch_k<XT, CT, PR, 4, 1>(a, counter, st);
-        case 1: return launch_batch_k<XT, CT, PR, 4, 2>(a, counter, st);
-        case 2: return launch_batch_k<XT, CT, PR, 5, 1>(a, counter, st);
-        case 3: return launch_batch_k<XT, CT, PR, 5, 2>(a, counter, st);
-        case 4: return launch_batch_k<XT, CT, PR, 6, 1>(a, counter, st);
-        case 5: return launch_batch_k<XT, CT, PR, 6, 2>(a, counter, st);
-        case 6: return launch_batch_k<XT, CT, PR, 7, 1>(a, counter, st);
-        case 7: return launch_batch_k<XT, CT, PR, 7, 2>(a, counter, st);
-        case 8: return launch_batch_k<XT, CT, PR, 8, 1>(a, counter, st);
-        default: return launch_batch_k<XT, CT, PR, 8, 2>(a, counter, st);
+    switch (v % 15 / 3) {
+        case 0: return launch_batch_nk<XT, CT, PR, 4>(v, a, counter, st);
+        case 1: return launch_batch_nk<XT, CT, PR, 5>(v, a, counter, st);
+        case 2: return launch_batch_nk<XT, CT, PR, 6>(v, a, counter, st);
+        case 3: return launch_batch_nk<XT, CT, PR, 7>(v, a, counter, st);
+        default: return launch_batch_nk<XT, CT, PR, 8>(v, a, counter, st);
     }
 }
 
 template <int CT>
 hipError_t launch_batch_variant(int v, const BatchArgs& a, int* counter, hipStream_t st) {
-    switch (v / 10) {
+    switch (v / 15) {
         case 0: return launch_batch_pr<XT_CI8, CT, PR_I>(v, a, counter, st);
         case 1: return launch_batch_pr<XT_CI8, CT, PR_IQUV>(v, a, counter, st);
         case 2: return launch_batch_pr<XT_CI16, CT, PR_I>(v, a, counter, st);

@@ -14,6 +14,7 @@
 #include "bf_addr.h"
 #include "lbf_device.h"
 #include "lbf_launch.h"
+#include "tile_table.h"
 
 #define LBF_INLINE __device__ __forceinline__
 
@@ -596,16 +597,26 @@ LBF_INLINE WaveTiles wave_tiles(int wave, int T, int t_int) {
     return w;
 }
 
-// Sample streams of the fast FP16/BF16 worker: one for more than 128 beams
-// (work items of 256 beams), else two (items of 128 beams).  Complex f32
-// samples always take one: a 16-byte chunk holds a single sample, and the
-// loaders of two streams would need twice the registers.
-__host__ __device__ inline int fast_h_streams(const BlockDesc& d) {
-    return d.xtype == XT_CF32 || d.b1 - d.b0 > 128 ? 1 : 2;
-}
-
 // K-steps of 8 stations of the fast FP16/BF16 worker: 4 to 8, the fewest that hold the stations (at least 4)
 __host__ __device__ inline int fast_h_ksteps(int S) { return S <= 32 ? 4 : (S + 7) / 8; }
+
+// Sample streams of the fast FP16/BF16 worker, the tile shape of its work
+// items: 1, 2 or 4 streams of 32-sample tiles beside 8, 4 or 2 beam tiles of
+// 32 (items of 256, 128 or 64 beams).  Fewer beams per item leave fewer waves
+// idle when a block has few beams, and more streams give every step more
+// samples to load; the measured table (tile_table.h) picks the count by
+// input type, product, K-steps and beams of the block part.  Complex f32 samples
+// always take one: a 16-byte chunk holds a single sample, and the loaders of
+// more streams would need more registers.  A process-wide override serves
+// the tuning sweep (g_tile_streams_override, lbf_set_tile_streams).
+inline int fast_h_streams(const BlockDesc& d) {
+    if (d.xtype == XT_CF32) return 1;
+    if (g_tile_streams_override) return g_tile_streams_override;
+    const int nb = d.b1 - d.b0;
+    int bucket = 0;
+    while (bucket < 4 && nb > kTileBeamMax[bucket]) ++bucket;
+    return kTileStreams[d.xtype == XT_CI8 ? 0 : 1][d.product == PR_I ? 0 : 1][fast_h_ksteps(d.S) - 4][bucket];
+}
 
 // A block whose beams beyond the last whole 256-beam group number at most 128
 // is taken in two parts: the 256-beam groups, and the rest as 128-beam items

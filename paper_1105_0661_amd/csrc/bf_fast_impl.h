@@ -60,10 +60,10 @@ inline void launch_h_nsi(const BlockDesc& d, int nbg, int n, hipStream_t st) {
 }
 
 // the INC form (incoherent beam beside the Stokes products) only for Stokes
-// with two sample streams (fuses_incoherent)
+// with several sample streams (fuses_incoherent)
 template <int XT, int CT, int PR, int TI, int NS>
 inline void launch_h_ns(const BlockDesc& d, int nbg, int n, hipStream_t st) {
-    if constexpr (PR != PR_VOLT && NS == 2) {
+    if constexpr (PR != PR_VOLT && NS >= 2) {
         if (d.inc != nullptr) {
             launch_h_nsi<XT, CT, PR, TI, NS, true>(d, nbg, n, st);
             return;
@@ -77,8 +77,10 @@ inline hipError_t launch_h_k(const BlockDesc& d, int nbg, int n, hipStream_t st)
     if constexpr (XT == XT_CF32) {
         launch_h_ns<XT, CT, PR, TI, 1>(d, nbg, n, st);      // complex f32: one stream (fast_h_streams)
     } else {
-        if (fast_h_streams(d) == 1) launch_h_ns<XT, CT, PR, TI, 1>(d, nbg, n, st);
-        else launch_h_ns<XT, CT, PR, TI, 2>(d, nbg, n, st);
+        const int ns = fast_h_streams(d);
+        if (ns == 1) launch_h_ns<XT, CT, PR, TI, 1>(d, nbg, n, st);
+        else if (ns == 2) launch_h_ns<XT, CT, PR, TI, 2>(d, nbg, n, st);
+        else launch_h_ns<XT, CT, PR, TI, 4>(d, nbg, n, st);
     }
     return hipGetLastError();
 }

@@ -94,7 +94,7 @@ hipError_t staging_alloc(void** p, size_t bytes, hipStream_t st) {
 bool needs_staging(const BlockDesc& d) { return fast_path(d) && d.product != PR_VOLT && d.order == 0; }
 
 bool fuses_incoherent(const BlockDesc& d) {
-    return fast_path(d) && d.ctype != CT_F32 && d.product != PR_VOLT && fast_h_streams(d) == 2;
+    return fast_path(d) && d.ctype != CT_F32 && d.product != PR_VOLT && fast_h_streams(d) >= 2;
 }
 
 size_t staging_channel_bytes(const BlockDesc& d) {

@@ -345,7 +345,8 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
             // the channel into the next one, or past the last valid station
             // (out of range: zeros), never past the array
             const __amdgpu_buffer_rsrc_t rs = group_rsrc(d.x, ch.s & ~7, S, stride_bytes);
-            const uint32_t off = sample_off(ch.s & 7, stride_bytes, c, T, ch.tile * kTile + ch.q * SPC, BYTES);
+            const uint32_t off =
+                ch.live ? sample_off(ch.s & 7, stride_bytes, c, T, ch.tile * kTile + ch.q * SPC, BYTES) : kNoStore;
             dst[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
         }
     };
@@ -378,8 +379,8 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     const int trow = tile_row_sample(r);
     const int sw = a_swz(trow);
     // two accumulator sets, unless the loaders' registers leave no room
-    // (complex int16 with two streams, more than two chunks per thread)
-    constexpr bool PIPE = !(XT == XT_CI16 && NS == 2) && CPT <= 2;
+    // (complex int16 with several streams, more than two chunks per thread)
+    constexpr bool PIPE = !(XT == XT_CI16 && NS >= 2) && CPT <= 2;
     constexpr int NOUT = PR == PR_VOLT ? 1 : 16 / TI;
 
     // incoherent beam of the item's tiles (INC form, first beam group only)

@@ -20,10 +20,13 @@ hipError_t launch_beamform(const BlockDesc& d, hipStream_t st);
 // channels; hipErrorInvalidValue if not one channel fits).
 bool needs_staging(const BlockDesc& d);
 // The block's incoherent beam is formed by its contraction: the fast FP16/BF16
-// worker with two sample streams (at most 128 beams, HBM-bound).  With more
+// worker with several sample streams (items of at most 128 beams, HBM-bound).  With more
 // beams that worker is bound by MFMA and VALU work, and a separate read of
 // the samples costs less than the extra work in every item (measured).
 bool fuses_incoherent(const BlockDesc& d);
+// 1, 2 or 4: sample streams of every FP16/BF16 fast work item; 0: the
+// measured tile table (set by lbf_set_tile_streams)
+extern int g_tile_streams_override;
 size_t staging_channel_bytes(const BlockDesc& d);
 int staging_chunk(const BlockDesc& d, size_t cap);
 hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, hipStream_t st);

@@ -107,6 +107,7 @@ _PROTOS = {
                                              ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                              ctypes.c_void_p]),
     "lbf_block_footprint": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.POINTER(BlockSizes)]),
+    "lbf_set_tile_streams": (ctypes.c_int, [ctypes.c_int]),
     "lbf_check_addressing": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_uint64)]),
     "lbf_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
@@ -421,6 +422,12 @@ def dedisperse_stokes(y, chirp, n_fft: int, product: int, t_int: int, out=None, 
     _check(lib().lbf_dedisperse_stokes(_dev_ptr(y, "y"), C, B, T, n_fft, _dev_ptr(chirp, "chirp"), product, t_int,
                                        _dev_ptr(out, "out"), _stream(stream)))
     return out
+
+
+def set_tile_streams(streams: int):
+    """lbf_set_tile_streams: force 1, 2 or 4 sample streams per FP16/BF16
+    work item (0: the measured table).  A tuning hook; results do not change."""
+    _check(lib().lbf_set_tile_streams(streams))
 
 
 def block_footprint(S: int, C: int, T: int, B: int, xtype: int, ctype: int, product: int, t_int: int = 1,

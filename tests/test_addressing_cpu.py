@@ -68,3 +68,31 @@ def test_staging_below_one_channel_is_refused():
 def test_blocks_outside_the_fast_path_walk_nothing():
     assert lbf.check_addressing(100, 2, 64, 30, lbf.CI8, lbf.F16, lbf.STOKES_I, 16) == 0     # > 64 stations
     assert lbf.check_addressing(20, 4, 64, 30, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 2) == 0   # channel integration
+
+
+@pytest.fixture
+def streams():
+    yield lbf.set_tile_streams
+    lbf.set_tile_streams(0)
+
+
+@pytest.mark.parametrize("ns", [1, 2, 4])
+def test_every_tile_shape_stays_inside_its_buffers(ns, streams):
+    # the FP16/BF16 worker's items of 256, 128 and 64 beams (1, 2, 4 sample
+    # streams, forced) on the integer-sample shapes above and the uneven
+    # batch's observations
+    streams(ns)
+    for S, C, T, B, xt, prod, ti in TEST_SHAPES:
+        if xt != "cf32":
+            _walk(S, C, T, B, xt, lbf.F16, prod, ti)
+    for js in synth.config3_jobs()[:6]:
+        _walk(js.S, js.nsb * js.nch, js.T, js.B, js.xtype, lbf.F16, lbf.PRODUCT_NAMES[js.product], js.t_int)
+
+
+def test_set_tile_streams_takes_only_item_shapes(streams):
+    for bad in (3, 8, -1):
+        with pytest.raises(lbf.LbfError) as ei:
+            streams(bad)
+        assert ei.value.code == lbf.E_INVAL
+    for ok in (0, 1, 2, 4):
+        streams(ok)
