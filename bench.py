@@ -46,6 +46,8 @@ def parse():
                    help="profiling run: time only the 488-beam block paths (no JSON line)")
     p.add_argument("--serve-seconds", type=float, default=60.0, help="measured seconds of the streaming run")
     p.add_argument("--serve-warmup", type=float, default=5.0, help="warm-up seconds of the streaming run")
+    p.add_argument("--profile-batch", action="store_true",
+                   help="profiling run: time only the uneven batch (no JSON line)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="counter calibration run: three plain 1 GiB device-to-device copies (no JSON line)")
     return p.parse_args()
@@ -654,6 +656,12 @@ def main():
                 continue
             r = time_path(lbf, torch, x2, geo2, ct, lbf.STOKES_IQUV, 16, 1, a.steps, a.warmup)
             log("precision %s: beam former %.3f ms" % (name, np.mean(r["beamform_ms"])))
+        return
+
+    if a.profile_batch:
+        jobs = make_jobs(lbf, torch, synth, dev)
+        r = batched(lbf, torch, jobs, a.steps, a.warmup)
+        log("batched: %.3f ms per batch, sequential %.3f ms" % (r["ms_per_batch"], r["ms_sequential"]))
         return
 
     # ---------------- the one-second block ----------------

@@ -18,7 +18,21 @@
 
 namespace lbf {
 
-constexpr int kSegTiles = 24;   // 32-sample tiles per work item at most
+// Work items cut a block's samples into segments of kSegTiles 32-sample
+// tiles, or of 2, 4 or 8 times as many while the block keeps at least
+// kMinItems items that way: a longer item spreads its prologue (weights into
+// registers, the first loads) and its last step over more steps, and enough
+// items remain to keep every compute unit busy to the end.
+constexpr int kSegTiles = 24, kSegTilesMax = 192, kMinItems = 2048;
+
+LBF_HD int seg_tiles(const BlockDesc& d, int nbg) {
+    const int ntiles = (d.T + kTile - 1) / kTile;
+    int seg = kSegTiles;
+    while (seg < kSegTilesMax && seg < ntiles &&
+           (int64_t)d.nc * nbg * ((ntiles + 2 * seg - 1) / (2 * seg)) >= kMinItems)
+        seg *= 2;
+    return seg;
+}
 
 // "no store": an offset past every output descriptor, which the hardware
 // drops.  2^31, not 2^32 - 1: the range check adds the access size to the
@@ -26,20 +40,21 @@ constexpr int kSegTiles = 24;   // 32-sample tiles per work item at most
 constexpr uint32_t kNoStore = 0x80000000u;
 
 // A work item of the fast workers: channel c (of [c0, c0 + nc)), beam group
-// bg, sample tiles [tile_lo, tile_lo + ntiles).
+// bg, sample tiles [tile_lo, tile_lo + ntiles) (nbg beam groups).
 struct ItemPos {
     int c, bg, tile_lo, ntiles;
 };
 
 LBF_HD ItemPos item_pos(const BlockDesc& d, int item, int nbg) {
     const int ntiles_all = (d.T + kTile - 1) / kTile;
-    const int nseg = (ntiles_all + kSegTiles - 1) / kSegTiles;
+    const int seg = seg_tiles(d, nbg);
+    const int nseg = (ntiles_all + seg - 1) / seg;
     ItemPos p;
     p.c = d.c0 + item / nseg / nbg;
     p.bg = item / nseg % nbg;
-    p.tile_lo = item % nseg * kSegTiles;
+    p.tile_lo = item % nseg * seg;
     const int left = ntiles_all - p.tile_lo;
-    p.ntiles = left < kSegTiles ? left : kSegTiles;
+    p.ntiles = left < seg ? left : seg;
     return p;
 }
 

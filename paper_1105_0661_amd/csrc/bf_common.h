@@ -633,22 +633,22 @@ inline int split_fast_h(const BlockDesc& d, BlockDesc* part) {
 }
 
 // Work items of the fast FP16/BF16 worker: (channel of [c0, c0 + nc), group
-// of 256/NS beams, segment of up to kSegTiles 32-sample tiles) -- long blocks
-// are cut in time so that few-channel blocks still spread over all compute
+// of 256/NS beams, segment of 32-sample tiles: seg_tiles) -- long blocks are
+// cut in time so that few-channel blocks still spread over all compute
 // units.
 inline int block_items_fast_h(const BlockDesc& d, int* nbg) {
     const int per = 8 / fast_h_streams(d) * kTile;
     *nbg = (d.b1 - d.b0 + per - 1) / per;
-    const int ntiles = (d.T + kTile - 1) / kTile;
-    return d.nc * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
+    const int ntiles = (d.T + kTile - 1) / kTile, seg = seg_tiles(d, *nbg);
+    return d.nc * *nbg * ((ntiles + seg - 1) / seg);
 }
 
 // work items of the fast FP32 worker: (channel of [c0, c0 + nc), group of 128
 // beams, segment)
 inline int block_items_fast_f32(const BlockDesc& d, int* nbg) {
     *nbg = (d.B + kBeamGroup - 1) / kBeamGroup;
-    const int ntiles = (d.T + kTile - 1) / kTile;
-    return d.nc * *nbg * ((ntiles + kSegTiles - 1) / kSegTiles);
+    const int ntiles = (d.T + kTile - 1) / kTile, seg = seg_tiles(d, *nbg);
+    return d.nc * *nbg * ((ntiles + seg - 1) / seg);
 }
 
 // number of (channel group, beam group) work items of a block

@@ -24,8 +24,8 @@ namespace lbf {
 
 // FP32 operands (MFMA 32x32x2 f32: one station per MFMA, K = (re, im)).
 //
-// A work item is one channel, 128 beams and a segment of up to kSegTiles
-// sample tiles; a work group has 8 waves (two per SIMD).  The weights of the
+// A work item is one channel, 128 beams and a segment of sample tiles
+// (seg_tiles); a work group has 8 waves (two per SIMD).  The weights of the
 // 128 beams sit in LDS as three planes p0 = w_re, p1 = -w_im, p2 = w_im
 // ([beam][station] rows), so that lane half h (the K index) multiplies the
 // plain sample component a = (h ? x_im : x_re) by  wr = (h ? p1 : p0)  for
@@ -303,7 +303,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     constexpr int CPS = kTile / SPC;                       // chunks per station per tile
     constexpr int CPTILE = 8 * NK * CPS;                   // chunks per tile
     constexpr int CPT = (NS * CPTILE + kThreadsH - 1) / kThreadsH;   // chunks per thread per step
-    // item = (channel, beam group, segment of up to kSegTiles sample tiles)
+    // item = (channel, beam group, segment of sample tiles: seg_tiles)
     const int T = d.T;
     const ItemPos ip = item_pos(d, item, nbg);             // tiles [tile_lo, tile_lo + ntiles)
     const int c = ip.c, bg = ip.bg, tile_lo = ip.tile_lo, ntiles = ip.ntiles;

@@ -53,9 +53,10 @@ def test_uneven_batch_observations_stay_inside_their_buffers(j):
     C = js.nsb * js.nch
     n = _walk(js.S, C, js.T, js.B, js.xtype, lbf.F16, prod, js.t_int)
     # the same block through staging of a few channels at a time (the server's
-    # and the no-allocation path's channel passes)
+    # and the no-allocation path's channel passes): every access of the whole
+    # block again, and more where a pass's fewer items take shorter segments
     per = lbf.block_footprint(js.S, C, js.T, js.B, X[js.xtype], lbf.F16, prod, js.t_int).staging_channel_bytes
-    assert _walk(js.S, C, js.T, js.B, js.xtype, lbf.F16, prod, js.t_int, staging_cap=7 * per) == n
+    assert _walk(js.S, C, js.T, js.B, js.xtype, lbf.F16, prod, js.t_int, staging_cap=7 * per) >= n
 
 
 def test_staging_below_one_channel_is_refused():
