@@ -116,11 +116,9 @@ void walk_h(Walk& w, const BlockDesc& d, int lo, int hi) {
                 for (int i = 0; i < CPT; ++i) {
                     const Chunk16 ch = h_chunk(tid + kThreadsH * i, k, NS, CPTILE, CPS, ip.tile_lo, ip.ntiles);
                     const int s0 = ch.s & ~7, t = ch.tile * kTile + ch.q * SPC;
-                    const uint64_t o64 =
-                        ch.live ? (uint64_t)(ch.s & 7) * stride64 + ((uint64_t)ip.c * d.T + t) * bytes : kNoStore;
+                    const uint64_t o64 = (uint64_t)(ch.s & 7) * stride64 + ((uint64_t)ip.c * d.T + t) * bytes;
                     w.access("sample load", group_base(s0, stride), group_range(s0, d.S, stride), o64,
-                             ch.live ? sample_off(ch.s & 7, stride, ip.c, d.T, t, bytes) : kNoStore, 16, xbuf,
-                             false);
+                             sample_off(ch.s & 7, stride, ip.c, d.T, t, bytes), 16, xbuf, false);
                 }
             for (int k = 0; k < nsteps; ++k) {
                 const int tile = ip.tile_lo + sigma + NS * k;

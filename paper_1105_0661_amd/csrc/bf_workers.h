@@ -345,8 +345,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
             // the channel into the next one, or past the last valid station
             // (out of range: zeros), never past the array
             const __amdgpu_buffer_rsrc_t rs = group_rsrc(d.x, ch.s & ~7, S, stride_bytes);
-            const uint32_t off =
-                ch.live ? sample_off(ch.s & 7, stride_bytes, c, T, ch.tile * kTile + ch.q * SPC, BYTES) : kNoStore;
+            const uint32_t off = sample_off(ch.s & 7, stride_bytes, c, T, ch.tile * kTile + ch.q * SPC, BYTES);
             dst[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
         }
     };
