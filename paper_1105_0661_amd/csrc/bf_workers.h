@@ -216,9 +216,11 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
 //     Re y = a . wr,   Im y = a . wi.
 // The samples of each 32-sample tile are loaded once per work group with
 // 16-byte loads, converted once, and left in LDS (double buffered, one
-// barrier per step) for all beam tiles to read.  Waves 4-7 defer each tile's
-// Stokes epilogue to the next step, so on every SIMD one wave's epilogue
-// (VALU) runs while the other wave's MFMAs do.
+// barrier per step) for all beam tiles to read.  Each wave runs a tile's
+// epilogue between the MFMAs of its next tile (two accumulator sets), or,
+// where the registers hold only one set, waves 4-7 run it at the start of
+// the next step, so on every SIMD one wave's epilogue (VALU) meets the
+// other wave's MFMAs.
 constexpr int kARow = 68;                          // words per (sample, polarisation) row of an A tile
 constexpr int kATileWords = kTile * 2 * kARow;     // 17 KB
 
@@ -528,10 +530,17 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
         // second): MFMAs, then the epilogue.
         // The samples of step j sit in rr[j % 2], loaded two steps ahead.
         floatx16 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = zero16();
         u32x4 rr[2][CPT];
         load_chunks_to(1, rr[1]);
+        // waves 4-7 (the second wave of each SIMD) run a tile's epilogue at
+        // the start of the next step, so that on every SIMD one wave's
+        // epilogue (VALU) meets the other wave's MFMAs
+        const bool late = wave >= 4;
         auto plain_step = [&](int k, u32x4 (&mine)[CPT], u32x4 (&next)[CPT]) {
             load_chunks_to(k + 2, mine);                       // mine held step k's samples, now in LDS
+            if (late) final_epilogue(acc, k - 1);
             int rowx = (sigma * 2 + (k & 1)) * kATileWords + 2 * trow * kARow;
             __asm__ volatile("" : "+v"(rowx));
             const uint32_t* ax0 = at + rowx;
@@ -550,7 +559,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
                 inc_finish(k - 1);
                 inc_partial(k);
             }
-            final_epilogue(acc, k);
+            if (!late) final_epilogue(acc, k);
 #pragma unroll
             for (int i = 0; i < CPT; ++i) store_chunk_from(k + 1, i, next);
             __syncthreads();
@@ -561,6 +570,7 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
             plain_step(k + 1, rr[1], rr[0]);
         }
         if (k < nsteps) plain_step(k, rr[0], rr[1]);
+        if (late) final_epilogue(acc, nsteps - 1);
         if (INC && inc_on) inc_finish(nsteps - 1);
         return;
     }

@@ -26,13 +26,13 @@ constexpr unsigned char kTileStreams[2][2][5][5] = {
         {   // ci16, Stokes I, K-steps 4..8
             {4, 4, 2, 1, 1},
             {4, 4, 2, 1, 1},
-            {4, 4, 2, 1, 1},
+            {4, 2, 2, 1, 1},
             {2, 2, 2, 1, 1},
             {2, 2, 2, 1, 1}},
         {   // ci16, Stokes IQUV, K-steps 4..8
             {4, 4, 2, 1, 1},
             {4, 4, 2, 1, 1},
-            {4, 4, 2, 1, 1},
+            {2, 2, 2, 1, 1},
             {2, 2, 2, 1, 1},
             {2, 2, 2, 1, 1}}}};
 
