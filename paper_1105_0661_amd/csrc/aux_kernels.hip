@@ -281,8 +281,66 @@ __global__ __launch_bounds__(256) void transpose_kernel(const E* __restrict__ in
     }
 }
 
+// The same reorder with 16-byte accesses (Q = T2 K and C2 multiples of the
+// elements per 16 bytes, both buffers 16-byte aligned): for one beam b, a
+// tile of 64 channels x 64 consecutive (t, k) values moves through LDS;
+// reads are 64-element runs of one channel's (t, k) values, writes 64-element
+// runs of channels of one (k, t) row of the final order.
+template <typename E>
+__global__ __launch_bounds__(256) void reorder_final_vec_kernel(const E* __restrict__ in, int C2, int B, int T2, int K,
+                                                                E* __restrict__ out) {
+    constexpr int V = 16 / sizeof(E);            // elements per 16-byte access
+    constexpr int LPR = 64 / V;                  // lanes per 64-element row
+    constexpr int RPP = 256 / LPR;               // rows per pass
+    __shared__ E tile[64][65];
+    const long Q = (long)T2 * K;
+    const long q0 = (long)blockIdx.x * 64;
+    const int c0 = blockIdx.y * 64, b = blockIdx.z;
+    const int l = threadIdx.x % LPR, rr = threadIdx.x / LPR;
+#pragma unroll
+    for (int p = 0; p < 64 / RPP; ++p) {
+        const int r = p * RPP + rr, c = c0 + r;
+        const long q = q0 + V * l;
+        if (c < C2 && q < Q) {
+            const floatx4 v = *reinterpret_cast<const floatx4*>(in + ((size_t)c * B + b) * Q + q);
+            const E* e = reinterpret_cast<const E*>(&v);
+#pragma unroll
+            for (int i = 0; i < V; ++i) tile[r][V * l + i] = e[i];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 64 / RPP; ++p) {
+        const int r = p * RPP + rr;
+        const long q = q0 + r;
+        const int c = c0 + V * l;
+        if (q < Q && c < C2) {
+            const long t = q / K;
+            const int k = (int)(q - t * K);
+            floatx4 v;
+            E* e = reinterpret_cast<E*>(&v);
+#pragma unroll
+            for (int i = 0; i < V; ++i) e[i] = tile[V * l + i][r];
+            *reinterpret_cast<floatx4*>(out + (((size_t)b * K + k) * T2 + t) * C2 + c) = v;
+        }
+    }
+}
+
 hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int elem_bytes, void* out,
                             hipStream_t st) {
+    const long Q = (long)T2 * K;
+    const int V = 16 / elem_bytes;
+    if (Q % V == 0 && C2 % V == 0 && B <= 65535 && (Q + 63) / 64 < (1L << 31) &&
+        (((uintptr_t)in | (uintptr_t)out) & 15) == 0) {
+        dim3 g((unsigned)((Q + 63) / 64), (unsigned)((C2 + 63) / 64), (unsigned)B), b(256);
+        if (elem_bytes == 4)
+            hipLaunchKernelGGL(reorder_final_vec_kernel<float>, g, b, 0, st, (const float*)in, C2, B, T2, K,
+                               (float*)out);
+        else
+            hipLaunchKernelGGL(reorder_final_vec_kernel<float2>, g, b, 0, st, (const float2*)in, C2, B, T2, K,
+                               (float2*)out);
+        return hipGetLastError();
+    }
     const long M = (long)B * T2 * K;
     dim3 g((unsigned)((M + 31) / 32), (unsigned)((C2 + 31) / 32)), b(256);
     if (elem_bytes == 4)

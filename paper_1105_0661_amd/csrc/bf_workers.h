@@ -314,6 +314,10 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
     const int bt = wave % NBT, sigma = wave / NBT;         // beam tile, sample stream
     const int S = d.S, bend = d.b1;
     const int beam = d.b0 + (bg * NBT + bt) * kTile + r;
+    // a wave whose beam tile lies wholly past the block's beams forms nothing
+    // (it still loads, stages and meets the barriers): its SIMD partner has
+    // the matrix pipe to itself
+    const bool idle = d.b0 + (bg * NBT + bt) * kTile >= d.b1;
     const int nsteps = (ntiles + NS - 1) / NS;
     const uint32_t stride_bytes = (uint32_t)((size_t)d.C * T * BYTES);
     const int T2 = PR == PR_VOLT ? T : T / TI;
@@ -513,6 +517,15 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
         }
         __syncthreads();
     };
+    // the step of an idle wave: the loaders' and the incoherent beam's share only
+    auto idle_step = [&](int k) {
+        load_chunks(k + 1);
+        if (INC && inc_on) inc_partial(k);
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) store_chunk(k + 1, i);
+        if (INC && inc_on) inc_finish(k - 1);
+        __syncthreads();
+    };
     // the last tile's epilogue: one more step without MFMAs
     auto final_epilogue = [&](const floatx16 (&prev)[4], int klast) {
         const int tile = tile_lo + sigma + NS * klast;
@@ -540,6 +553,16 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
         const bool late = wave >= 4;
         auto plain_step = [&](int k, u32x4 (&mine)[CPT], u32x4 (&next)[CPT]) {
             load_chunks_to(k + 2, mine);                       // mine held step k's samples, now in LDS
+            if (idle) {
+                if (INC && inc_on) {
+                    inc_finish(k - 1);
+                    inc_partial(k);
+                }
+#pragma unroll
+                for (int i = 0; i < CPT; ++i) store_chunk_from(k + 1, i, next);
+                __syncthreads();
+                return;
+            }
             if (late) final_epilogue(acc, k - 1);
             int rowx = (sigma * 2 + (k & 1)) * kATileWords + 2 * trow * kARow;
             __asm__ volatile("" : "+v"(rowx));
@@ -570,7 +593,12 @@ LBF_INLINE void item_h_fast(const BlockDesc& d, int item, int nbg, uint32_t* at)
             plain_step(k + 1, rr[1], rr[0]);
         }
         if (k < nsteps) plain_step(k, rr[0], rr[1]);
-        if (late) final_epilogue(acc, nsteps - 1);
+        if (late && !idle) final_epilogue(acc, nsteps - 1);
+        if (INC && inc_on) inc_finish(nsteps - 1);
+        return;
+    }
+    if (idle) {
+        for (int k = 0; k < nsteps; ++k) idle_step(k);
         if (INC && inc_on) inc_finish(nsteps - 1);
         return;
     }

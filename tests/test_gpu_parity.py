@@ -263,15 +263,27 @@ def test_unfused_chain_matches_oracle_and_fused():
 
 
 def test_transpose_is_exact():
+    # element-wise kernel (rows that 16-byte accesses do not fit, or
+    # misaligned buffers) and the 16-byte tile kernel, with ragged tiles of
+    # both: channels and (t, k) values not multiples of 64
     torch = _torch()
     g = torch.Generator(device="cuda:0").manual_seed(3)
-    a = torch.randn((37, 5, 9, 4), device="cuda:0", generator=g)
+    for shape in [(37, 5, 9, 4), (196, 5, 12, 4), (128, 7, 20, 1), (68, 2, 33, 4), (4, 1, 1, 4)]:
+        a = torch.randn(shape, device="cuda:0", generator=g)
+        o = lbf.transpose(a)
+        torch.cuda.synchronize()
+        assert torch.equal(o, a.permute(1, 3, 2, 0).contiguous()), shape
+    for shape in [(33, 3, 70, 2, 2), (66, 3, 70, 2, 2), (130, 2, 65, 2, 2)]:
+        v = torch.randn(shape, device="cuda:0", generator=g)
+        ov = lbf.transpose(v)
+        torch.cuda.synchronize()
+        assert torch.equal(ov, v.permute(1, 3, 2, 0, 4).contiguous()), shape
+    # a buffer 4 bytes off 16-byte alignment takes the element-wise kernel
+    base = torch.randn(196 * 5 * 12 * 4 + 1, device="cuda:0", generator=g)
+    a = base[1:].view(196, 5, 12, 4)
     o = lbf.transpose(a)
-    v = torch.randn((33, 3, 70, 2, 2), device="cuda:0", generator=g)
-    ov = lbf.transpose(v)
     torch.cuda.synchronize()
     assert torch.equal(o, a.permute(1, 3, 2, 0).contiguous())
-    assert torch.equal(ov, v.permute(1, 3, 2, 0, 4).contiguous())
 
 
 @pytest.mark.parametrize("ctype,S,product,t_int,f_int", [
