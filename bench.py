@@ -455,6 +455,42 @@ def make_jobs(lbf, torch, synth, dev, log_every=4):
     return jobs
 
 
+def precision_errors(lbf, torch, b2, x2, geo2):
+    """Voltage and Stokes errors of the precision block's FP16 and BF16 paths
+    against the FP64 oracle, on the subband that holds the first tone (256
+    channels x 488 beams x 768 samples; the whole block's voltages would be
+    49 GB, and the work is linear in the channels)."""
+    from oracle import oracle as orc
+    nthreads, _ = host_threads()
+    sb = b2.tones[0].channel // b2.nch
+    chans = np.arange(sb * b2.nch, (sb + 1) * b2.nch)
+    xs = np.ascontiguousarray(b2.x[:, chans])
+    t0 = time.perf_counter()
+    vref = orc.pipeline(xs, b2.station_xyz, b2.beam_dir, b2.ref_dir, b2.freq_hz[chans], 0, 1, 1, nthreads)
+    sref = orc.pipeline(xs, b2.station_xyz, b2.beam_dir, b2.ref_dir, b2.freq_hz[chans], 4, 16, 1, nthreads)
+    cpu_s = time.perf_counter() - t0
+    xd = x2[:, torch.from_numpy(chans).to(x2.device)].contiguous()
+    pos, dirs, freq, ref = geo2
+    out = {"sample": "subband %d (channels %d..%d, holding a tone), all 488 beams and 768 samples; oracle %.1f s "
+                     "on %d threads" % (sb, chans[0], chans[-1], cpu_s, nthreads)}
+    vr = vref                                                 # [B][2][T][C] complex128
+    for name, ct in (("f16", lbf.F16), ("bf16", lbf.BF16)):
+        w = lbf.compute_weights(pos, dirs, freq[torch.from_numpy(chans).to(x2.device)].contiguous(), ct, ref_dir=ref)
+        y = lbf.beamform(xd, w, lbf.VOLTAGES)                 # [C][B][T][2][2]
+        st = lbf.beamform(xd, w, lbf.STOKES_IQUV, 16, 1)      # [B][4][T'][C]
+        torch.cuda.synchronize()
+        yc = y.cpu().numpy().astype(np.float64)
+        yc = (yc[..., 0] + 1j * yc[..., 1]).transpose(1, 3, 2, 0)   # [B][2][T][C]
+        got = st.cpu().numpy()
+        out[name] = {"voltages_rel_l2": float(np.linalg.norm(yc - vr) / np.linalg.norm(vr)),
+                     "voltages_max_over_rms": float(np.max(np.abs(yc - vr)) / np.sqrt(np.mean(np.abs(vr) ** 2))),
+                     "stokes_rel_l2": {k: relerr(got[:, i], sref[:, i]) for i, k in enumerate("IQUV")},
+                     "stokes_max_over_rms": {k: max_over_rms(got[:, i], sref[:, i]) for i, k in enumerate("IQUV")}}
+        del w, y, st
+    del xd
+    return out
+
+
 def batched(lbf, torch, jobs, steps, warmup):
     """One persistent launch over all jobs (lbf_beamform_batch) against one
     lbf_beamform per job, FP16 MFMA, weights resident."""
@@ -758,6 +794,9 @@ def main():
             if mp:
                 extra[name]["mfma_frac_of_measured_peak"] = extra[name]["mfma_TFLOPs"] / mp["f16_TFLOPs"]
             log("precision %s: %s" % (name, extra[name]))
+        if not a.no_cpu:
+            extra["errors_vs_oracle"] = precision_errors(lbf, torch, b2, x2, geo2)
+            log("precision errors: %s" % extra["errors_vs_oracle"])
         del b2.x
 
         # ---------------- uneven batch and streaming service ----------------

@@ -354,8 +354,8 @@ int lbf_check_addressing(const lbf_block* blk, int channel_major, uint64_t stagi
  * count and beam count (tiles.json, compiled into the library).  streams = 1,
  * 2 or 4 forces that shape for every later call in this process (complex f32
  * samples keep 1); 0 restores the table.  For the sweep that measures the
- * table; it changes only speed, never results.  Not synchronised with calls
- * running on other threads.
+ * table; it changes only speed, never results.  A call running on another
+ * thread meanwhile may take either setting.
  * Errors: LBF_E_INVAL for other values.
  */
 int lbf_set_tile_streams(int streams);

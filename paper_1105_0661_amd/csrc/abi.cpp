@@ -156,7 +156,7 @@ int lbf::run_batch(const lbf_block* blks, int n, void* const* stage, const size_
     return ok();
 }
 
-int lbf::g_tile_streams_override = 0;
+std::atomic<int> lbf::g_tile_streams_override{0};
 
 int lbf::set_error(int code, const char* fmt, ...) {
     char buf[512];
@@ -457,7 +457,7 @@ int lbf_check_addressing(const lbf_block* blk, int channel_major, uint64_t stagi
 int lbf_set_tile_streams(int streams) {
     if (streams != 0 && streams != 1 && streams != 2 && streams != 4)
         return fail(LBF_E_INVAL, "lbf_set_tile_streams: streams must be 0, 1, 2 or 4 (got %d)", streams);
-    lbf::g_tile_streams_override = streams;
+    lbf::g_tile_streams_override.store(streams, std::memory_order_relaxed);
     return ok();
 }
 

@@ -85,19 +85,17 @@ LBF_HD uint32_t weight_off(int beam, int S, int s, int bytes) { return ((uint32_
 // k covers stream sg, station s and samples SPC q .. SPC q + SPC - 1 of tile
 // `tile` (the stream's tile of that step, or its last tile once it has run
 // out).  Chunks past the step's ns tiles (a step of fewer chunks than
-// threads) are not live: they load the tiles of a later step (in range,
-// clamped to the item's last tile), which warms the cache for that step,
-// and are not staged.  (Skipping their loads, with an out-of-range offset,
-// costs registers that the two headline shapes do not have.)
+// threads) load the tiles of a later step (in range, clamped to the item's
+// last tile), which warms the cache for that step, and are not staged.
+// (Skipping their loads, with an out-of-range offset, costs registers that
+// the two headline shapes do not have.)
 struct Chunk16 {
     int s, q, tile;
-    bool live;
 };
 
 LBF_HD Chunk16 h_chunk(int j, int k, int ns, int cptile, int cps, int tile_lo, int ntiles) {
     const int sg = j / cptile, jt = j % cptile;
     Chunk16 ch;
-    ch.live = sg < ns;
     ch.s = jt / cps;
     ch.q = jt % cps;
     const int i = sg + ns * k;

@@ -611,7 +611,7 @@ __host__ __device__ inline int fast_h_ksteps(int S) { return S <= 32 ? 4 : (S + 
 // the tuning sweep (g_tile_streams_override, lbf_set_tile_streams).
 inline int fast_h_streams(const BlockDesc& d) {
     if (d.xtype == XT_CF32) return 1;
-    if (g_tile_streams_override) return g_tile_streams_override;
+    if (const int o = g_tile_streams_override.load(std::memory_order_relaxed)) return o;
     const int nb = d.b1 - d.b0;
     int bucket = 0;
     while (bucket < 4 && nb > kTileBeamMax[bucket]) ++bucket;

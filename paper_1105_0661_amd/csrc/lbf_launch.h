@@ -1,6 +1,8 @@
 // lbf_launch.h -- host-side launchers of the lbf kernels (internal).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include "lbf_device.h"
 
 namespace lbf {
@@ -26,7 +28,7 @@ bool needs_staging(const BlockDesc& d);
 bool fuses_incoherent(const BlockDesc& d);
 // 1, 2 or 4: sample streams of every FP16/BF16 fast work item; 0: the
 // measured tile table (set by lbf_set_tile_streams)
-extern int g_tile_streams_override;
+extern std::atomic<int> g_tile_streams_override;
 size_t staging_channel_bytes(const BlockDesc& d);
 int staging_chunk(const BlockDesc& d, size_t cap);
 hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, hipStream_t st);
