@@ -68,9 +68,12 @@ def test_incoherent_form_of_every_stream_count(ns):
     the two kernels.  Same tied-array beams either way, incoherent beam
     against the oracle."""
     torch = _torch()
+    # (the last two leave whole beam tiles idle: with two streams, and with
+    # the one-accumulator form of complex int16)
     for i, (S, B, T, xt, prod, ti) in enumerate([(37, 100, 96, "ci8", lbf.STOKES_I, 4),
                                                  (64, 128, 64, "ci16", lbf.STOKES_IQUV, 16),
-                                                 (26, 40, 1100, "ci8", lbf.STOKES_IQUV, 2)]):
+                                                 (26, 40, 1100, "ci8", lbf.STOKES_IQUV, 2),
+                                                 (40, 20, 96, "ci16", lbf.STOKES_IQUV, 8)]):
         blk = synth.make_block(S, B, 1, 3, T, xt, 16.0 if xt == "ci8" else 40.0, tag=(1105, 661, 81 + i))
         x, w = to_dev(blk.x), _weights(blk, lbf.F16)
         lbf.set_tile_streams(ns)
