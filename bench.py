@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--serve-warmup", type=float, default=5.0, help="warm-up seconds of the streaming run")
     p.add_argument("--profile-batch", action="store_true",
                    help="profiling run: time only the uneven batch (no JSON line)")
+    p.add_argument("--profile-aux", action="store_true",
+                   help="profiling run: only the kernels beside the beam former -- incoherent beam, "
+                        "dedispersion, the case-E chain, channeliser, superstations (no JSON line)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="counter calibration run: three plain 1 GiB device-to-device copies (no JSON line)")
     return p.parse_args()
@@ -692,6 +695,18 @@ def main():
                 continue
             r = time_path(lbf, torch, x2, geo2, ct, lbf.STOKES_IQUV, 16, 1, a.steps, a.warmup)
             log("precision %s: beam former %.3f ms" % (name, np.mean(r["beamform_ms"])))
+        return
+
+    if a.profile_aux:
+        blk = synth.config1(threads=16)
+        x = torch.from_numpy(blk.x).to(dev)
+        del blk.x
+        log("incoherent beam: %s" % incoherent(lbf, torch, x, a.steps, a.warmup, None))
+        del x
+        log("dedispersion: %s" % dedispersion(lbf, torch, dev, a.steps, a.warmup, None))
+        log("pulsar chain (case E): %s" % pulsar_chain(lbf, torch, synth, dev, a.steps, a.warmup, None))
+        log("channeliser: %s" % channelizer(lbf, torch, dev, a.steps, a.warmup, None))
+        log("superstations: %s" % superstations(lbf, torch, dev, a.steps, a.warmup, None))
         return
 
     if a.profile_batch:
