@@ -286,7 +286,9 @@ __global__ __launch_bounds__(kDdThreads) void dedisperse_kernel(const floatx4* _
                                                                 floatx4* __restrict__ out, int B, int T) {
     __shared__ __attribute__((aligned(16))) cfl buf[2 * lds_words<N>()];
     const int nb = T / N;
-    const long wg = blockIdx.x;
+    // consecutive (beam, block) groups of a channel on one XCD: its chirp
+    // is then fetched into that XCD's L2 once rather than into every L2
+    const long wg = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const long cb = wg / nb;                                // c B + b
     const int blk = (int)(wg - cb * nb);
     const int c = (int)(cb / B);
@@ -330,7 +332,9 @@ __global__ __launch_bounds__(kDdThreads) void dedisperse_stokes_kernel(const flo
                                                                        float* __restrict__ s, int B, int T, int t_int) {
     __shared__ __attribute__((aligned(16))) cfl buf[2 * lds_words<N>()];
     const int nb = T / N;
-    const long wg = blockIdx.x;
+    // consecutive (beam, block) groups of a channel on one XCD: its chirp
+    // is then fetched into that XCD's L2 once rather than into every L2
+    const long wg = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const long cb = wg / nb;                                // c B + b
     const int blk = (int)(wg - cb * nb);
     const int c = (int)(cb / B);
