@@ -255,23 +255,32 @@ def channelizer(lbf, torch, dev, steps, warmup, mp, geo=None):
     S, NSB, nch = 64, 32, 256
     T_sb = 768 * nch
     gen = torch.Generator(device=dev).manual_seed(1105661)
-    x = torch.randint(-300, 301, (S, NSB, T_sb, 2, 2), generator=gen, device=dev, dtype=torch.int16)
+    # rows 64 samples longer than the window, so that shifted windows stay inside them
+    x = torch.randint(-300, 301, (S, NSB, T_sb + 64, 2, 2), generator=gen, device=dev, dtype=torch.int16)
+    shift = torch.randint(0, 64, (S,), generator=gen, device=dev, dtype=torch.int32)
     out = torch.empty((S, NSB * nch, T_sb // nch, 2, 2), dtype=torch.float32, device=dev)
     nrep = warmup + steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(nrep)]
-    for i in range(nrep):
-        ev[i][0].record()
-        lbf.channelize(x, nch, out=out)
-        ev[i][1].record()
-    torch.cuda.synchronize()
-    ms = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(warmup, nrep)]))
+
+    def timed(sh):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(nrep)]
+        for i in range(nrep):
+            ev[i][0].record()
+            lbf.channelize(x, nch, t_sb=T_sb, shift=sh, out=out)
+            ev[i][1].record()
+        torch.cuda.synchronize()
+        return float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(warmup, nrep)]))
+
+    ms = timed(None)
+    ms_shift = timed(shift)
     nbytes = S * NSB * T_sb * 8 + S * NSB * T_sb * 16
     gbps = nbytes / (ms / 1e3) / 1e9
     r = {"workload": "channeliser of the one-second block: 64 stations, 32 subbands x 196608 complex int16 "
                      "samples, 2 pols -> 256 channels per subband, complex f32",
          "kernel_ms": ms, "algorithmic_bytes": nbytes, "hbm_GBps": gbps, "bound": "hbm",
          "frac": gbps / PEAK["hbm_GBps"],
-         "input_Gbps": S * NSB * T_sb * 64 / (ms / 1e3) / 1e9}
+         "input_Gbps": S * NSB * T_sb * 64 / (ms / 1e3) / 1e9,
+         "kernel_ms_with_station_shifts": ms_shift,
+         "station_shifts": "seeded per-station whole-sample shifts U{0..63} (delay compensation)"}
     if mp:
         r["frac_of_measured_hbm"] = gbps / max(mp["hbm_GBps"], mp["hbm_read_GBps"])
     if geo is not None:
@@ -284,7 +293,7 @@ def channelizer(lbf, torch, dev, steps, warmup, mp, geo=None):
             ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nrep)]
             for i in range(nrep):
                 ev[i][0].record()
-                lbf.channelize(x, nch, out=out)
+                lbf.channelize(x, nch, t_sb=T_sb, shift=shift, out=out)
                 ev[i][1].record()
                 lbf.beamform(out, w, lbf.STOKES_IQUV, 16, 1, out=bf)
                 ev[i][2].record()
@@ -297,8 +306,9 @@ def channelizer(lbf, torch, dev, steps, warmup, mp, geo=None):
                            / (bms / 1e3) / 1e9,
                            "beam_samples_per_s": B * NSB * nch * 768 / (tms / 1e3)}
             del w, bf
-        r["channelise_then_beamform"] = dict(chain, workload="channelise (above) -> lbf_beamform on the complex f32 "
-                                                             "channels: 128 beams, Stokes IQUV x16, final order")
+        r["channelise_then_beamform"] = dict(chain, workload="channelise with the station shifts (above) -> "
+                                                             "lbf_beamform on the complex f32 channels: 128 beams, "
+                                                             "Stokes IQUV x16, final order")
     del x, out
     return r
 

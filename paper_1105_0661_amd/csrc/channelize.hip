@@ -12,8 +12,9 @@
 // (station, subband) row, both polarisations, in LDS (33 KiB with padding,
 // so four groups share a compute unit):
 //   1. coalesced loads of the tile's samples (the station's shifted window),
-//      16-byte vectors of 1, 2 or 4 samples when the window is aligned and
-//      inside the row, single samples otherwise; converted to float;
+//      16-byte vectors of 1, 2 or 4 samples when the window, widened to
+//      16-byte boundaries, lies inside the row (any shift), single samples
+//      otherwise; converted to float;
 //   2. Stockham passes over the tile's kChTile / nch spectra: radix 16
 //      while four or more bits of nch remain, then radix 4, then radix 2
 //      (two radix-16 passes for 256 channels); each pass reads all its
@@ -136,18 +137,28 @@ __global__ __launch_bounds__(kChThreads) void channelize_kernel(const void* __re
     const long t_first = (long)t0 * nch + (shift ? shift[s] : 0);   // row sample of the tile's first
     constexpr int P = 16 / Sample<XT>::bytes;           // samples per 16-byte vector
     const size_t r0 = (size_t)row * Tin;
-    if (t_first >= 0 && t_first + nvalid <= Tin && (r0 + t_first) % P == 0 && nvalid % P == 0) {
-        // the window lies inside the row on a 16-byte boundary: P samples per lane and load
-        const intx4* xv = reinterpret_cast<const intx4*>(static_cast<const char*>(x) + (r0 + t_first) * Sample<XT>::bytes);
-        for (int iv = threadIdx.x; iv < kChTile / P; iv += kChThreads) {
+    // 16-byte vectors from the aligned sample at or before the window's first
+    // one (off samples earlier) to past its last, when all of them lie inside
+    // the row
+    const int off = t_first >= 0 ? (int)((r0 + t_first) % P) : 0;
+    const int nv = (off + nvalid + P - 1) / P;
+    if (t_first >= off && t_first + nvalid <= Tin && t_first - off + (long)nv * P <= Tin) {
+        // P samples per lane and load; sample h of vector iv is tile sample
+        // iv P + h - off, zero past the window
+        const intx4* xv =
+            reinterpret_cast<const intx4*>(static_cast<const char*>(x) + (r0 + t_first - off) * Sample<XT>::bytes);
+        for (int iv = threadIdx.x; iv < (kChTile + off + P - 1) / P; iv += kChThreads) {
             intx4 q = {0, 0, 0, 0};
-            if (iv * P < nvalid) q = __builtin_nontemporal_load(xv + iv);
+            if (iv < nv) q = __builtin_nontemporal_load(xv + iv);
             float f[P][4];
             vec_samples<XT>(q, f);
 #pragma unroll
             for (int h = 0; h < P; ++h) {
-                buf[lds_index(iv * P + h)] = mk(f[h][0], f[h][1]);
-                buf[kChWords + lds_index(iv * P + h)] = mk(f[h][2], f[h][3]);
+                const int i = iv * P + h - off;
+                if (i < 0 || i >= kChTile) continue;
+                const bool in = i < nvalid;
+                buf[lds_index(i)] = mk(in ? f[h][0] : 0.f, in ? f[h][1] : 0.f);
+                buf[kChWords + lds_index(i)] = mk(in ? f[h][2] : 0.f, in ? f[h][3] : 0.f);
             }
         }
     } else {

@@ -105,6 +105,23 @@ def test_channelize_with_station_shifts_matches_oracle():
     _check(cplx(out), orc.channelize(x, nch, t_sb=T_sb, shift=shift))
 
 
+@pytest.mark.parametrize("xt,T_in", [("ci16", 3100), ("ci8", 3103), ("ci16", 3099), ("cf32", 3101)])
+def test_channelize_with_misaligned_shifts_matches_oracle(xt, T_in):
+    """Shifts that are not multiples of the samples in 16 bytes (2 for
+    complex int16, 4 for complex int8), odd row lengths, windows that end
+    exactly at the row's end or one sample before it, and a ragged last tile
+    (T_sb = 2048 + 976 samples)."""
+    torch = _torch()
+    S, NSB, nch = 6, 2, 16
+    T_sb = 3024
+    x = _subbands(S, NSB, T_in, xt, 23)
+    shift = np.array([1, 3, T_in - T_sb, T_in - T_sb - 1, 5, 2], np.int32)
+    flush("channelize misaligned shifts %s %s T_in=%d" % (xt, shift.tolist(), T_in))
+    out = lbf.channelize(to_dev(x), nch, t_sb=T_sb, shift=to_dev(shift))
+    torch.cuda.synchronize()
+    _check(cplx(out), orc.channelize(x, nch, t_sb=T_sb, shift=shift))
+
+
 def test_channelize_shift_aligns_a_delayed_station_bitwise():
     """Station 1 holds station 0's samples d later; shifted by d, its window
     holds the same numbers, so its channels are bit for bit station 0's."""
