@@ -116,11 +116,14 @@ typedef struct {
 /*
  * Run one block.  The Stokes products are fused: detection and integration
  * happen in the epilogue of the contraction kernel.  Blocks of at most 64
- * stations of complex int8/int16 with t_int <= 16 and no channel integration
- * (the fast workers) form them channel-major in a staging buffer taken from
- * the device's stream-ordered memory pool, then reorder them into the final
- * order: the same two steps as lbf_beamform_channel_major + lbf_beam_major.
- * Other blocks store the final order from the epilogue directly.
+ * stations with t_int <= 16 (the fast workers) form them channel-major in a
+ * staging buffer taken from the device's stream-ordered memory pool, then
+ * reorder them into the final order: the same two steps as
+ * lbf_beamform_channel_major + lbf_beam_major.  With channel integration
+ * (f_int a power of two up to 64) the fast workers stage each channel
+ * integrated in time, and the reorder sums each group of f_int channels in
+ * channel order.  Other blocks store the final order from the epilogue
+ * directly.
  * Errors: LBF_E_INVAL (sizes < 1, NULL pointers, T % t_int, C % f_int,
  * t_int/f_int != 1 for voltages, unknown enums); LBF_E_UNSUPPORTED for a Stokes
  * block whose t_int is not a power of two (use lbf_beamform with VOLTAGES,
@@ -158,7 +161,8 @@ int lbf_beamform_incoherent(const lbf_block* blk, float* d_inc, void* stream);
  * other threads) race and must be serialised by the caller.  Nothing in the
  * array needs to start at any value.
  * Errors: as lbf_beamform; LBF_E_NOMEM when one channel's staging
- * (T' x B x K floats, rows padded to a multiple of 32) exceeds the array.
+ * (T' x B x K floats, rows padded to a multiple of 32), times f_int with
+ * channel integration on the fast workers, exceeds the array.
  */
 #define LBF_NOALLOC_SCRATCH_BYTES (64ull << 20)
 int lbf_beamform_noalloc(const lbf_block* blk, void* stream);
@@ -170,6 +174,9 @@ int lbf_beamform_noalloc(const lbf_block* blk, void* stream);
  *   d_out  STOKES: f32 [C'][T'][B][K] (each beam's K parameters together, then
  *          the beams);  VOLTAGES: as lbf_beamform.
  * lbf_beam_major of this output equals lbf_beamform's output bit for bit.
+ * With channel integration on the fast workers the per-channel products go
+ * through staging from the stream-ordered pool, and the f_int channel sums
+ * (in channel order, as lbf_beamform's) are written from it.
  * Errors: as lbf_beamform.
  */
 int lbf_beamform_channel_major(const lbf_block* blk, void* stream);
@@ -365,9 +372,10 @@ typedef struct {
     uint64_t input_bytes, weight_bytes, output_bytes;
     double flops;          /* 8 flops per complex multiply-add, both polarisations */
     uint64_t staging_bytes;          /* Stokes staging lbf_beamform takes for the whole block
-                                        (the channel-major products before the reorder); 0 if none */
-    uint64_t staging_channel_bytes;  /* the same for one channel: the least staging a channel
-                                        pass needs                                            */
+                                        (the channel-major products before the reorder, one row
+                                        per channel before any channel sums); 0 if none        */
+    uint64_t staging_channel_bytes;  /* the same for one channel (a channel pass needs f_int of
+                                        them with channel integration)                        */
 } lbf_block_sizes;
 int lbf_block_footprint(const lbf_block* blk, lbf_block_sizes* out);
 

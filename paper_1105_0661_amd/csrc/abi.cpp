@@ -232,10 +232,10 @@ int lbf_beamform_noalloc(const lbf_block* blk, void* stream) {
     hipError_t e;
     if (lbf::needs_staging(d)) {
         const size_t per = lbf::staging_channel_bytes(d);
-        if (per > lbf::kNoAllocScratchBytes)
-            return fail(LBF_E_NOMEM, "lbf_beamform_noalloc: one channel's Stokes staging (%zu bytes: T' x B x K "
-                        "floats, rows padded to 32) exceeds the %llu-byte scratch", per,
-                        (unsigned long long)lbf::kNoAllocScratchBytes);
+        if (lbf::staging_chunk(d, lbf::kNoAllocScratchBytes) < 1)
+            return fail(LBF_E_NOMEM, "lbf_beamform_noalloc: the Stokes staging of one channel (%zu bytes: T' x B x K "
+                        "floats, rows padded to 32), times f_int with channel integration, exceeds the %llu-byte "
+                        "scratch", per, (unsigned long long)lbf::kNoAllocScratchBytes);
         void* scratch = nullptr;
         e = lbf::noalloc_scratch(&scratch);
         if (e != hipSuccess) return hip_fail(e, "lbf_beamform_noalloc: scratch address");

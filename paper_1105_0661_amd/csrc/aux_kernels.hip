@@ -1,5 +1,7 @@
 // aux_kernels.hip -- weights (FP64), unfused Stokes, final-order transpose and
 // the incoherent beam.
+#include <algorithm>
+
 #include "lbf_device.h"
 #include "lbf_launch.h"
 
@@ -424,6 +426,108 @@ hipError_t launch_stage_to_beam_major(const float* stage, int C2, int M, int B, 
         hipLaunchKernelGGL(stage_to_beam_major_kernel<true>, g, b, 0, st, stage, C2, M, B, ldb, out, ldo, walk);
     else
         hipLaunchKernelGGL(stage_to_beam_major_kernel<false>, g, b, 0, st, stage, C2, M, B, ldb, out, ldo, walk);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Channel integration out of the staging (Section 3, Section 5.1): the fast
+// workers stage each channel's Stokes parameters integrated in time, and the
+// sums over groups of F adjacent channels are formed here, in channel order,
+// while the staging is read once.  Both kernels add the F values in the same
+// order, so the two output orders hold the same bits.
+// ---------------------------------------------------------------------------
+
+// staging s[c][m][b] (rows of ldb, C2 channels, a multiple of F) ->
+// out[b][m][c'] (rows of ldo), c' = c / F.  A work group moves 64 channels x
+// 64 beams of one m through LDS: 256-byte reads along b (16 bytes per lane
+// where the rows allow it), then 64 / F consecutive sums per beam.
+template <bool VEC>
+__global__ __launch_bounds__(256) void stage_sum_to_beam_major_kernel(const float* __restrict__ in, int C2, int M, int B,
+                                                                      int ldb, int F, float* __restrict__ out,
+                                                                      size_t ldo) {
+    __shared__ float tile[64][65];
+    const size_t m = blockIdx.x;
+    const int c0 = blockIdx.y * 64, b0 = blockIdx.z * 64;
+    const int q = threadIdx.x & 15, rr = threadIdx.x >> 4;       // 16 lanes x 4 elements per row
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int r = p * 16 + rr, c = c0 + r, b = b0 + 4 * q;
+        if (c >= C2) continue;
+        const float* src = in + ((size_t)c * M + m) * ldb + b;
+        if (VEC && b + 3 < B) {
+            const floatx4 v = *reinterpret_cast<const floatx4*>(src);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tile[r][4 * q + e] = v[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (b + e < B) tile[r][4 * q + e] = src[e];
+        }
+    }
+    __syncthreads();
+    const int G = 64 / F;                                        // sums per beam in the tile
+    for (int v = threadIdx.x; v < 64 * G; v += 256) {
+        const int bl = v / G, g = v - bl * G;
+        const int b = b0 + bl, c = c0 + g * F;
+        if (b >= B || c >= C2) continue;                          // C2 is a multiple of F: the group is whole
+        float sum = tile[g * F][bl];
+        for (int j = 1; j < F; ++j) sum += tile[g * F + j][bl];
+        out[((size_t)b * M + m) * ldo + c / F] = sum;
+    }
+}
+
+hipError_t launch_stage_sum_to_beam_major(const float* stage, int C2, int M, int B, int ldb, int F, float* out,
+                                          size_t ldo, hipStream_t st) {
+    const dim3 g((unsigned)M, (unsigned)((C2 + 63) / 64), (unsigned)((B + 63) / 64)), b(256);
+    const bool aligned = (reinterpret_cast<uintptr_t>(stage) & 15) == 0;
+    if (aligned && ldb % 4 == 0)
+        hipLaunchKernelGGL(stage_sum_to_beam_major_kernel<true>, g, b, 0, st, stage, C2, M, B, ldb, F, out, ldo);
+    else
+        hipLaunchKernelGGL(stage_sum_to_beam_major_kernel<false>, g, b, 0, st, stage, C2, M, B, ldb, F, out, ldo);
+    return hipGetLastError();
+}
+
+// staging s[c][m][b] (rows of ldb, C2 channels) -> out[c'][m][b] (rows of B):
+// one thread per 4 consecutive b (16-byte loads and stores) where the rows
+// and buffers allow it, else per b.
+template <bool VEC>
+__global__ __launch_bounds__(256) void stage_sum_channels_kernel(const float* __restrict__ in, int C2, int M, int B,
+                                                                 int ldb, int F, float* __restrict__ out) {
+    const int BV = VEC ? B / 4 : B;
+    const size_t n = (size_t)(C2 / F) * M * BV;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int bv = (int)(i % BV);
+        const size_t cm = i / BV;
+        const size_t m = cm % M;
+        const size_t co = cm / M;
+        const float* src = in + ((size_t)co * F * M + m) * ldb;
+        float* dst = out + (co * M + m) * (size_t)B;
+        if (VEC) {
+            floatx4 sum = *reinterpret_cast<const floatx4*>(src + 4 * bv);
+            for (int j = 1; j < F; ++j) {
+                const floatx4 v = *reinterpret_cast<const floatx4*>(src + (size_t)j * M * ldb + 4 * bv);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sum[e] += v[e];
+            }
+            *reinterpret_cast<floatx4*>(dst + 4 * bv) = sum;
+        } else {
+            float sum = src[bv];
+            for (int j = 1; j < F; ++j) sum += src[(size_t)j * M * ldb + bv];
+            dst[bv] = sum;
+        }
+    }
+}
+
+hipError_t launch_stage_sum_channels(const float* stage, int C2, int M, int B, int ldb, int F, float* out,
+                                     hipStream_t st) {
+    const bool vec = ((reinterpret_cast<uintptr_t>(stage) | reinterpret_cast<uintptr_t>(out)) & 15) == 0 &&
+                     ldb % 4 == 0 && B % 4 == 0;
+    const size_t n = (size_t)(C2 / F) * M * (vec ? B / 4 : B);
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 1u << 20);
+    if (vec)
+        hipLaunchKernelGGL(stage_sum_channels_kernel<true>, dim3(grid), dim3(256), 0, st, stage, C2, M, B, ldb, F, out);
+    else
+        hipLaunchKernelGGL(stage_sum_channels_kernel<false>, dim3(grid), dim3(256), 0, st, stage, C2, M, B, ldb, F, out);
     return hipGetLastError();
 }
 

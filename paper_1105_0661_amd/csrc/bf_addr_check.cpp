@@ -214,7 +214,7 @@ bool check_fast_addressing(const BlockDesc& d, int threads, uint64_t* accesses, 
 int check_block_addressing(const BlockDesc& d0, bool channel_major, size_t cap, int threads, uint64_t* accesses,
                            char* msg, size_t msglen) {
     if (accesses) *accesses = 0;
-    if (!fast_path(d0)) return 0;
+    if (!fast_path(d0) && !fast_path_fint(d0)) return 0;
     BlockDesc d = d0;
     if (channel_major) d.order = 1;
     BlockDesc passes[1];
@@ -231,6 +231,7 @@ int check_block_addressing(const BlockDesc& d0, bool channel_major, size_t cap, 
         if (staged) {
             passes[0].order = 1;
             passes[0].ld_row = staging_ld(d.B, d.product == PR_IQUV ? 4 : 1);
+            passes[0].f_int = 1;                           // channel sums follow, out of the staging
             passes[0].c0 = c0;
             passes[0].nc = d.C - c0 < nc ? d.C - c0 : nc;
         }

@@ -679,6 +679,17 @@ __host__ __device__ inline bool fast_path(const BlockDesc& d) {
     return 8.0 * (double)d.C * (double)d.T * sample_bytes(d.xtype) < 2147483648.0 - 4096.0;
 }
 
+// A Stokes block with channel integration (f_int a power of two up to 64)
+// whose channels the fast workers can form one at a time: their per-channel
+// products (integrated in time only) go through staging, and the pass out of
+// the staging sums each group of f_int channels.
+__host__ __device__ inline bool fast_path_fint(const BlockDesc& d) {
+    if (d.product == PR_VOLT || d.f_int < 2 || d.f_int > 64 || (d.f_int & (d.f_int - 1))) return false;
+    BlockDesc e = d;
+    e.f_int = 1;
+    return fast_path(e);
+}
+
 // Descriptor over the planes of the valid stations of group [s0, s0 + 8)
 // (group_base, group_range): offsets of stations >= S are out of range and
 // read as zero; a group with no valid station has range 0.

@@ -91,7 +91,13 @@ hipError_t staging_alloc(void** p, size_t bytes, hipStream_t st) {
 // 16-byte store per beam and period for IQUV); a beam-major block (order 0)
 // goes through a staging buffer of that layout, rows padded to a multiple of
 // 32 floats, and a tiled transpose.
-bool needs_staging(const BlockDesc& d) { return fast_path(d) && d.product != PR_VOLT && d.order == 0; }
+// Stokes staging: the final order from the fast workers (the reorder follows
+// them), and channel integration on the fast workers in either order (the
+// channel sums follow them)
+bool needs_staging(const BlockDesc& d) {
+    if (d.product == PR_VOLT) return false;
+    return (d.order == 0 && fast_path(d)) || fast_path_fint(d);
+}
 
 bool fuses_incoherent(const BlockDesc& d) {
     return fast_path(d) && d.ctype != CT_F32 && d.product != PR_VOLT && fast_h_streams(d) >= 2;
@@ -104,13 +110,15 @@ size_t staging_channel_bytes(const BlockDesc& d) {
 
 // Channels per pass through a staging buffer of `cap` bytes: all of them if
 // they fit, else the most that fit rounded down to a multiple of 64 (or 4), so
-// that the reorder keeps its 16-byte stores; 0 if not even one channel fits.
+// that the reorder keeps its 16-byte stores, and always whole groups of f_int
+// channels (f_int a power of two up to 64); 0 if not even one group fits.
 int staging_chunk(const BlockDesc& d, size_t cap) {
     const size_t n = cap / staging_channel_bytes(d);
+    const int F = d.product == PR_VOLT ? 1 : d.f_int;
     if (n >= (size_t)d.C) return d.C;
     if (n >= 64) return (int)(n / 64 * 64);
-    if (n >= 4) return (int)(n / 4 * 4);
-    return (int)n;
+    if (n >= 4 && F <= 4) return (int)(n / 4 * 4);
+    return (int)(n / F * F);
 }
 
 hipError_t launch_beamform_direct(const BlockDesc& d, hipStream_t st) {
@@ -120,11 +128,15 @@ hipError_t launch_beamform_direct(const BlockDesc& d, hipStream_t st) {
 
 // A block through caller-provided staging of `cap` bytes: the channels in
 // passes of staging_chunk(d, cap), each pass the contraction into the staging
-// buffer and the reorder of its channels into the final order; the passes are
-// ordered by the stream, so they reuse the buffer.
+// buffer (per channel, integrated in time) and then, out of the staging, the
+// reorder into the final order or, with channel integration, the sums over
+// each group of f_int channels (in channel order, into the final order or the
+// channel-major one); the passes are ordered by the stream, so they reuse the
+// buffer.
 hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, hipStream_t st) {
     if (!needs_staging(d)) return launch_beamform_direct(d, st);
     const int K = d.product == PR_IQUV ? 4 : 1;
+    const int F = d.f_int;
     const int T2 = d.T / d.t_int;
     const int ld = staging_ld(d.B, K);
     const int nc = staging_chunk(d, cap);
@@ -134,13 +146,20 @@ hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, h
         ds.out = stage;
         ds.order = 1;
         ds.ld_row = ld;
+        ds.f_int = 1;
         ds.c0 = c0;
         ds.nc = d.C - c0 < nc ? d.C - c0 : nc;
         hipError_t e = launch_fast(ds, st);
-        // [c][t'][b k] -> [b k][t'][c]: the beam-major final order [b][k][t'][c]
-        if (e == hipSuccess)
+        if (e != hipSuccess) return e;
+        if (d.order == 1)          // [c][t'][b k] -> channel sums [c'][t'][b k] (rows of B K floats)
+            e = launch_stage_sum_channels((const float*)stage, ds.nc, T2, d.B * K, ld, F,
+                                          (float*)d.out + (size_t)(c0 / F) * T2 * d.B * K, st);
+        else if (F == 1)           // [c][t'][b k] -> [b k][t'][c]: the beam-major final order [b][k][t'][c]
             e = launch_stage_to_beam_major((const float*)stage, ds.nc, T2, d.B * K, ld, (float*)d.out + c0,
                                            (size_t)d.C, st);
+        else                       // the same with the channel sums
+            e = launch_stage_sum_to_beam_major((const float*)stage, ds.nc, T2, d.B * K, ld, F,
+                                               (float*)d.out + c0 / F, (size_t)(d.C / F), st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

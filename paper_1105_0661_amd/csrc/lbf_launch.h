@@ -32,6 +32,13 @@ extern std::atomic<int> g_tile_streams_override;
 size_t staging_channel_bytes(const BlockDesc& d);
 int staging_chunk(const BlockDesc& d, size_t cap);
 hipError_t launch_beamform_staged(const BlockDesc& d, void* stage, size_t cap, hipStream_t st);
+// staging [c][m][ldb] of C2 channels -> out[b][m][c'] (rows of ldo), c' = c / F,
+// each output the sum over its F channels in channel order
+hipError_t launch_stage_sum_to_beam_major(const float* stage, int C2, int M, int B, int ldb, int F, float* out,
+                                          size_t ldo, hipStream_t st);
+// staging [c][m][ldb] of C2 channels -> out[c'][m][B] (dense rows), the same sums
+hipError_t launch_stage_sum_channels(const float* stage, int C2, int M, int B, int ldb, int F, float* out,
+                                     hipStream_t st);
 hipError_t launch_beamform_direct(const BlockDesc& d, hipStream_t st);   // blocks that need no staging
 // The fixed staging array of lbf_beamform_noalloc on the current device: its
 // device address (looked up once per device, with that device current).

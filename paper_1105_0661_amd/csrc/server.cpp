@@ -642,8 +642,11 @@ int lbf_server_submit(lbf_server* s, const lbf_job* job, uint64_t* ticket) {
     if (!s || !ticket) return set_error(LBF_E_INVAL, "lbf_server_submit: NULL argument");
     int rc = validate_job(job);
     if (rc) return rc;
-    if (stage_channel_bytes(*job) > stage_cap(s->cfg))
-        return set_error(LBF_E_NOMEM, "lbf_server_submit: one channel's Stokes staging exceeds staging_cap");
+    // a channel pass holds whole groups of f_int channels (channel integration)
+    const uint64_t group = job->product == LBF_VOLTAGES ? 1 : (uint64_t)job->f_int;
+    if (stage_channel_bytes(*job) * group > stage_cap(s->cfg))
+        return set_error(LBF_E_NOMEM, "lbf_server_submit: the Stokes staging of one channel (of f_int channels "
+                         "with channel integration) exceeds staging_cap");
     if (weights_alloc_bytes(*job) + align_up(staging_bytes(*job)) + stream_max_bytes(*job) +
             align_up(stage_need(s->cfg, *job)) > s->cfg.arena_bytes)
         return set_error(LBF_E_NOMEM, "lbf_server_submit: job footprint exceeds the arena");

@@ -137,8 +137,11 @@ def test_footprint_arithmetic():
     assert v.staging_bytes == 0                                                           # voltages: none
     g = lbf.block_footprint(100, 8, 64, 40, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 1)       # > 64 stations: generic
     assert g.staging_bytes == 0
-    f = lbf.block_footprint(40, 8, 64, 40, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 2)         # channel integration
-    assert f.staging_bytes == 0
+    # channel integration on the fast workers: one staging row per channel (before the channel sums)
+    f = lbf.block_footprint(40, 8, 64, 40, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 2)
+    assert f.staging_channel_bytes == 4 * 64 * 4 and f.staging_bytes == 8 * 4 * 64 * 4
+    f3 = lbf.block_footprint(40, 9, 64, 40, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 3)        # f_int 3: generic, none
+    assert f3.staging_bytes == 0
 
 
 def _table1():

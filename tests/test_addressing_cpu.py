@@ -68,7 +68,24 @@ def test_staging_below_one_channel_is_refused():
 
 def test_blocks_outside_the_fast_path_walk_nothing():
     assert lbf.check_addressing(100, 2, 64, 30, lbf.CI8, lbf.F16, lbf.STOKES_I, 16) == 0     # > 64 stations
-    assert lbf.check_addressing(20, 4, 64, 30, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 2) == 0   # channel integration
+    assert lbf.check_addressing(20, 6, 64, 30, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 3) == 0   # f_int not a power of 2
+    assert lbf.check_addressing(20, 128, 64, 30, lbf.CI8, lbf.F16, lbf.STOKES_I, 16, 128) == 0   # f_int > 64
+
+
+@pytest.mark.parametrize("fi", [2, 4, 16, 64])
+def test_channel_integration_walks_per_channel_staging(fi):
+    # the fast workers form each channel integrated in time into staging, in
+    # passes of whole f_int-channel groups, in either output order
+    C = 128
+    n = _walk(20, C, 96, 70, "ci16", lbf.F16, lbf.STOKES_IQUV, 16, fi)
+    assert _walk(20, C, 96, 70, "ci16", lbf.F16, lbf.STOKES_IQUV, 16, fi, channel_major=True) == n
+    assert n == _walk(20, C, 96, 70, "ci16", lbf.F16, lbf.STOKES_IQUV, 16, 1)      # the same accesses as f_int 1
+    per = lbf.block_footprint(20, C, 96, 70, lbf.CI16, lbf.F16, lbf.STOKES_IQUV, 16, fi).staging_channel_bytes
+    assert per > 0
+    assert _walk(20, C, 96, 70, "ci16", lbf.F16, lbf.STOKES_IQUV, 16, fi, staging_cap=fi * per) >= n
+    with pytest.raises(lbf.LbfError) as ei:
+        lbf.check_addressing(20, C, 96, 70, lbf.CI16, lbf.F16, lbf.STOKES_IQUV, 16, fi, staging_cap=fi * per - 4)
+    assert ei.value.code == lbf.E_NOMEM
 
 
 @pytest.fixture

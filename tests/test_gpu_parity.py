@@ -262,6 +262,29 @@ def test_unfused_chain_matches_oracle_and_fused():
     assert ei.value.code == lbf.E_UNSUPPORTED
 
 
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
+@pytest.mark.parametrize("product,t_int,f_int", [(lbf.STOKES_IQUV, 16, 2), (lbf.STOKES_I, 4, 4),
+                                                 (lbf.STOKES_IQUV, 8, 16), (lbf.STOKES_I, 16, 64)])
+def test_channel_integration_on_the_fast_workers(ctype, product, t_int, f_int):
+    """Channel integration (f_int a power of two up to 64) on the fast
+    workers: each channel integrated in time into staging, then the f_int
+    channel sums -- against the oracle, the same bits in both output orders
+    and through lbf_beamform_noalloc."""
+    torch = _torch()
+    xtype = "ci8" if ctype != lbf.F32 else "ci16"
+    blk = synth.make_block(37, 70, 2, 64, 128, xtype, 16.0 if xtype == "ci8" else 40.0, tag=(1105, 661, 78))
+    flush("channel integration %s K=%d t_int=%d f_int=%d" % (CT_NAMES[ctype], product, t_int, f_int))
+    x, w = to_dev(blk.x), _weights(blk, ctype)
+    out = lbf.beamform(x, w, product, t_int, f_int)
+    cm = lbf.beamform_channel_major(x, w, product, t_int, f_int)
+    na = lbf.beamform_noalloc(x, w, product, t_int, f_int)
+    torch.cuda.synchronize()
+    assert torch.equal(lbf.beam_major(cm), out)
+    assert torch.equal(na, out)
+    _check_stokes(out.cpu().numpy(), _oracle_stokes(blk, product, t_int, f_int), TOL[ctype], "channel integration",
+                  blk, ctype, t_int, f_int)
+
+
 def test_transpose_is_exact():
     # element-wise kernel (rows that 16-byte accesses do not fit, or
     # misaligned buffers) and the 16-byte tile kernel, with ragged tiles of
@@ -291,7 +314,7 @@ def test_transpose_is_exact():
     (lbf.F16, 33, lbf.STOKES_I, 4, 1),          # fast FP16 worker
     (lbf.BF16, 11, lbf.STOKES_IQUV, 8, 1),      # fast BF16 worker
     (lbf.F16, 70, lbf.STOKES_IQUV, 16, 1),      # generic worker (> 64 stations)
-    (lbf.F32, 11, lbf.STOKES_IQUV, 2, 2),       # generic worker (channel integration)
+    (lbf.F32, 11, lbf.STOKES_IQUV, 2, 2),       # fast worker, channel sums out of the staging
     (lbf.BF16, 9, lbf.STOKES_I, 64, 1),         # generic worker (t_int >= 32)
 ], ids=["f32-fast", "f16-fast", "bf16-fast", "f16-S70", "f32-fint2", "bf16-tint64"])
 def test_channel_major_then_beam_major_equals_fused(ctype, S, product, t_int, f_int):

@@ -22,6 +22,7 @@ MIX = [
     (31, 1, 1, 5, 48, "ci16", lbf.STOKES_I, 4, 1, 4),
     (70, 90, 1, 4, 64, "ci8", lbf.STOKES_IQUV, 16, 2, 5),     # > 64 stations, channel integration
     (24, 17, 2, 16, 64, "ci8", lbf.STOKES_I, 16, 1, 1),       # same observation as the first: cached weights
+    (48, 70, 2, 16, 64, "ci16", lbf.STOKES_IQUV, 16, 4, 6),   # channel integration on the fast workers
 ]
 
 
@@ -167,6 +168,35 @@ def test_admission_waits_for_stokes_staging():
     check_stokes(outs[0].cpu().numpy(), ref, TOL[lbf.F16], "staging wait")
     assert torch.equal(outs[0], outs[1])
     assert torch.equal(passes, outs[0])
+
+
+@pytest.mark.parametrize("ctype", [lbf.F16, lbf.F32], ids=["f16", "f32"])
+def test_channel_integration_through_staging_passes(ctype):
+    # channel integration on the fast workers: per-channel staging in passes
+    # of whole f_int-channel groups (4 channels of a 6-channel cap), the same
+    # bits as lbf_beamform; a cap below one group is refused at submit
+    torch = _torch()
+    blk = synth.make_block(40, 100, 2, 16, 64, "ci8", 16.0, tag=(1105, 661, 79))
+    prod, ti, fi = lbf.STOKES_IQUV, 16, 4
+    x = to_dev(blk.x)
+    w = lbf.compute_weights(to_dev(blk.station_xyz), to_dev(blk.beam_dir), to_dev(blk.freq_hz), ctype,
+                            ref_dir=blk.ref_dir)
+    direct = lbf.beamform(x, w, prod, ti, fi)
+    per = lbf.block_footprint(blk.S, blk.C, blk.T, blk.B, lbf.CI8, ctype, prod, ti, fi).staging_channel_bytes
+    assert per > 0
+    flush("server channel integration passes %s" % CT_NAMES[ctype])
+    with lbf.Server(_arena(64 << 20), max_inflight=1, n_streams=1, staging_cap=6 * per) as srv:
+        t = _submit(srv, blk, prod, ti, fi, 79, ctype, x)
+        assert srv.wait(t).state == lbf.JOB_DONE
+        got = srv.output(t).clone()
+    with lbf.Server(_arena(64 << 20), max_inflight=1, n_streams=1, staging_cap=3 * per) as srv:
+        with pytest.raises(lbf.LbfError) as ei:
+            _submit(srv, blk, prod, ti, fi, 79, ctype, x)
+        assert ei.value.code == lbf.E_NOMEM
+    torch.cuda.synchronize()
+    assert torch.equal(got, direct)
+    ref = orc.pipeline(blk.x, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz, prod, ti, fi, 8)
+    check_stokes(got.cpu().numpy(), ref, TOL[ctype], "channel integration passes")
 
 
 def test_queue_status_codes():
