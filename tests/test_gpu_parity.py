@@ -448,6 +448,24 @@ def test_beamform_with_incoherent_beam(case):
         check_close(got[None], inc2.cpu().numpy()[None], 1e-6, "fused vs lbf_incoherent")
 
 
+def test_beamform_incoherent_with_channel_integration():
+    """Channel integration: the tied-array beams through the staged channel
+    sums, the incoherent beam by lbf_incoherent -- beams bitwise lbf_beamform,
+    incoherent beam against the oracle."""
+    torch = _torch()
+    blk = synth.make_block(30, 50, 2, 8, 64, "ci8", 16.0, tag=(1105, 661, 77))
+    x, w = to_dev(blk.x), _weights(blk, lbf.F16)
+    flush("beamform + incoherent with f_int 4")
+    out, inc = lbf.beamform_incoherent(x, w, lbf.STOKES_IQUV, 8, 4)
+    alone = lbf.beamform(x, w, lbf.STOKES_IQUV, 8, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(out, alone)
+    ref = orc.incoherent(blk.x, 4, 8, 4)                          # [C'][T'][K]
+    got = inc.cpu().numpy()                                       # [K][T'][C']
+    for k in range(4):
+        check_close(got[k].T[None], ref[..., k][None], 1e-5, "incoherent %s" % "IQUV"[k])
+
+
 def test_beamform_incoherent_rejects_voltages_and_overlap():
     torch = _torch()
     blk = synth.make_block(8, 10, 1, 2, 64, "ci8", 16.0, tag=(1105, 661, 69))
