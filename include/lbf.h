@@ -361,8 +361,9 @@ int lbf_check_addressing(const lbf_block* blk, int channel_major, uint64_t stagi
  * count and beam count (tiles.json, compiled into the library).  streams = 1,
  * 2 or 4 forces that shape for every later call in this process (complex f32
  * samples keep 1); 0 restores the table.  For the sweep that measures the
- * table; it changes only speed, never results.  A call running on another
- * thread meanwhile may take either setting.
+ * table; it changes only speed, never results.  Each call reads the setting
+ * once, when it starts, so a call that runs on another thread meanwhile takes
+ * the old setting or the new one throughout.
  * Errors: LBF_E_INVAL for other values.
  */
 int lbf_set_tile_streams(int streams);

@@ -85,6 +85,7 @@ lbf::BlockDesc to_desc(const lbf_block* b) {
     d.c0 = 0;
     d.nc = b->C;
     d.inc = nullptr;
+    d.ns_force = lbf::g_tile_streams_override.load(std::memory_order_relaxed);
     return d;
 }
 

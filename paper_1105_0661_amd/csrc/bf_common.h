@@ -608,10 +608,11 @@ __host__ __device__ inline int fast_h_ksteps(int S) { return S <= 32 ? 4 : (S + 
 // input type, product, K-steps and beams of the block part.  Complex f32 samples
 // always take one: a 16-byte chunk holds a single sample, and the loaders of
 // more streams would need more registers.  A process-wide override serves
-// the tuning sweep (g_tile_streams_override, lbf_set_tile_streams).
+// the tuning sweep (lbf_set_tile_streams): each call copies it into its
+// BlockDesc once (ns_force), so every part of one call sees the same value.
 inline int fast_h_streams(const BlockDesc& d) {
     if (d.xtype == XT_CF32) return 1;
-    if (const int o = g_tile_streams_override.load(std::memory_order_relaxed)) return o;
+    if (d.ns_force) return d.ns_force;
     const int nb = d.b1 - d.b0;
     int bucket = 0;
     while (bucket < 4 && nb > kTileBeamMax[bucket]) ++bucket;

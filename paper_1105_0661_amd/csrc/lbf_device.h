@@ -36,6 +36,8 @@ struct BlockDesc {
     int c0, nc;         // fast workers: channels [c0, c0 + nc) (0, C for a whole block); their output
                         // holds channel c at index c - c0
     float* inc;         // FP16/BF16 fast worker, Stokes: also the incoherent beam [K][T'][C], or NULL
+    int ns_force;       // FP16/BF16 fast worker: sample streams per item forced for this call (1, 2, 4),
+                        // or 0 for the tile table; read once when the call starts
 };
 
 // ---------------------------------------------------------------------------
