@@ -199,7 +199,10 @@ int lbf_beam_major(const float* d_in, int C2, int K, int T2, int B, float* d_out
  * than 64 stations) run through their own launches.  All launches go to
  * `stream`.  Each block's result is bitwise identical to lbf_beamform on that
  * block alone.  All blocks must be Stokes products with one ctype, F16 or
- * BF16.  n <= LBF_MAX_BATCH.
+ * BF16.  n <= LBF_MAX_BATCH.  Each call takes the next of 1024 work counters
+ * of its device, busy until the call's launches end: calls on one stream are
+ * ordered and never collide, but no more than 1024 calls may be outstanding
+ * at once on one device across different streams.
  * Errors: as lbf_beamform, per block; LBF_E_INVAL if n < 1 or n > LBF_MAX_BATCH;
  * LBF_E_UNSUPPORTED for voltages, F32 operands or mixed ctypes.
  */

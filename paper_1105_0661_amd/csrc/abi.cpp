@@ -90,7 +90,8 @@ lbf::BlockDesc to_desc(const lbf_block* b) {
 }
 
 // Work counters of the persistent batch kernel: a ring of slots per device so
-// that batches queued on different streams do not share a counter.
+// that batches queued on different streams do not share a counter (a slot
+// comes round again after kCounterSlots calls; the header states that limit).
 constexpr int kCounterSlots = 1024;
 std::mutex g_counter_mu;
 int* g_counters[64] = {nullptr};
