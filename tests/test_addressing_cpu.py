@@ -46,6 +46,17 @@ def test_parity_test_shapes_stay_inside_their_buffers(shape, ctype):
         _walk(S, C, T, B, xt, ctype, prod, ti, channel_major=True)
 
 
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16], ids=["f32", "f16"])
+def test_largest_fast_path_block_stays_inside_its_buffers(ctype):
+    """64 stations of complex int16, 4096 channels x 8176 samples: each
+    8-station plane group just under the 2^31-byte descriptor range (the GPU
+    parity test of the same shape); 16 samples more and the fast workers
+    decline the block (no accesses to walk: it goes to the generic workers)."""
+    assert _walk(64, 4096, 8176, 130, "ci16", ctype, lbf.STOKES_IQUV, 16) > 0
+    n = lbf.check_addressing(64, 4096, 8192, 130, X["ci16"], ctype, lbf.STOKES_IQUV, 16, 1, threads=THREADS)
+    assert n == 0
+
+
 @pytest.mark.parametrize("j", range(12))
 def test_uneven_batch_observations_stay_inside_their_buffers(j):
     js = synth.config3_jobs()[j]

@@ -12,6 +12,8 @@ largest error reaches about 12 tol rms, within its rounding bound.)  Pure data
 movement (transpose) and exactly representable cases are compared bit for
 bit.
 """
+import types
+
 import numpy as np
 import pytest
 
@@ -595,6 +597,41 @@ def test_precision_block_sampled(ctype):
     ev = relerr(cplx(y), yo)
     flush("  voltage rel err %s: %.3g" % (CT_NAMES[ctype], ev))
     _check_volt(cplx(y), yo, 3e-3, "precision block voltages")
+
+
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16], ids=lambda c: CT_NAMES[c])
+def test_largest_fast_path_block_sampled(ctype):
+    """The largest block the fast workers take: 64 stations whose 8-station
+    planes of complex int16 samples (4096 channels x 8176 samples) just fit
+    the 2^31-byte buffer descriptors, 130 beams, a ragged last sample tile of
+    16.  The first and last 256 samples of the first, middle and last
+    channels (the largest offsets) against the oracle.  Samples: seeded
+    Gaussian noise (sigma 64) drawn on the device, copied back for the
+    oracle."""
+    torch = _torch()
+    S, B, C, T = 64, 130, 4096, 8176
+    assert 8 * C * T * 8 < 2 ** 31 - 4096 < 8 * C * (T + 16) * 8
+    blk = synth.make_block(S, B, 16, 256, T, "ci16", generate=False)
+    flush("largest fast-path block %s: S=%d B=%d C=%d T=%d CI16 IQUV/16" % (CT_NAMES[ctype], S, B, C, T))
+    g = torch.Generator(device="cuda:0").manual_seed(20260)
+    x = torch.empty((S, C, T, 2, 2), dtype=torch.int16, device="cuda:0")
+    for s in range(S):
+        v = torch.randn((C, T, 2, 2), generator=g, device="cuda:0").mul_(64.0).round_()
+        x[s] = v.clamp_(-32768, 32767).to(torch.int16)
+        del v
+    w = _weights(blk, ctype)
+    out = lbf.beamform(x, w, lbf.STOKES_IQUV, 16, 1)                     # [B][4][T'][C]
+    torch.cuda.synchronize()
+    chans = np.array([0, 1, C // 2, C - 1])
+    idx = torch.from_numpy(chans).to("cuda:0")
+    for t0 in (0, T - 256):
+        xs = np.ascontiguousarray(x[:, idx, t0:t0 + 256].cpu().numpy())
+        got = out[:, :, t0 // 16:t0 // 16 + 16][:, :, :, idx].cpu().numpy()
+        ref = orc.pipeline(xs, blk.station_xyz, blk.beam_dir, blk.ref_dir, blk.freq_hz[chans], 4, 16, 1, 16)
+        part = types.SimpleNamespace(x=xs, S=S, station_xyz=blk.station_xyz, beam_dir=blk.beam_dir,
+                                     ref_dir=blk.ref_dir, freq_hz=blk.freq_hz[chans])
+        _check_stokes(got, ref, TOL[ctype], "largest block, samples %d.." % t0, part, ctype, 16, 1)
+    del x, w, out
 
 
 # --------------------------------------------------------------------------
