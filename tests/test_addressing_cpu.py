@@ -34,7 +34,8 @@ TEST_SHAPES = [(13, 5, 112, 70, "ci16", lbf.VOLTAGES, 1), (1, 3, 32, 37, "ci8", 
                (20, 3, 1100, 140, "ci8", lbf.STOKES_IQUV, 4), (20, 3, 1100, 50, "ci16", lbf.VOLTAGES, 1),
                (31, 5, 48, 1, "ci16", lbf.STOKES_I, 4), (64, 16, 768, 488, "ci8", lbf.STOKES_IQUV, 16),
                (12, 32, 64, 40, "cf32", lbf.STOKES_IQUV, 4), (13, 5, 112, 70, "cf32", lbf.VOLTAGES, 1),
-               (64, 256, 48, 128, "cf32", lbf.STOKES_IQUV, 16), (40, 6, 200, 150, "cf32", lbf.STOKES_I, 8)]
+               (64, 256, 48, 128, "cf32", lbf.STOKES_IQUV, 16), (40, 6, 200, 150, "cf32", lbf.STOKES_I, 8),
+               (1, 1, 1, 1, "ci16", lbf.STOKES_IQUV, 1), (2, 1, 1, 1, "ci16", lbf.VOLTAGES, 1)]
 
 
 @pytest.mark.parametrize("shape", TEST_SHAPES, ids=lambda s: "S%d_C%d_T%d_B%d_%s_K%d_t%d" % s)

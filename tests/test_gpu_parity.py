@@ -170,6 +170,27 @@ def test_fast_path_station_and_sample_edges(ctype, S, T):
 
 
 @pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
+@pytest.mark.parametrize("S", [1, 2, 65])
+def test_one_sample_one_channel_one_beam(ctype, S):
+    # the smallest block: one channel, one beam, one sample (one output sample
+    # of each Stokes parameter), on the fast workers (1, 2 stations) and the
+    # generic ones (65 stations)
+    torch = _torch()
+    blk = synth.make_block(S, 1, 1, 1, 1, "ci16", 40.0, tag=(1105, 661, 71))
+    flush("one sample %s S=%d" % (CT_NAMES[ctype], S))
+    x, w = to_dev(blk.x), _weights(blk, ctype)
+    y = lbf.beamform(x, w, lbf.VOLTAGES)
+    s1 = lbf.beamform(x, w, lbf.STOKES_I, 1, 1)
+    s4 = lbf.beamform(x, w, lbf.STOKES_IQUV, 1, 1)
+    torch.cuda.synchronize()
+    assert tuple(y.shape) == (1, 1, 1, 2, 2) and tuple(s4.shape) == (1, 4, 1, 1)
+    _check_volt(cplx(y), orc.beamform(blk.x, orc.block_weights(blk)), TOL[ctype], "one-sample voltages")
+    _check_stokes(s1.cpu().numpy(), _oracle_stokes(blk, 1, 1, 1), TOL[ctype], "one-sample I", blk, ctype, 1)
+    _check_stokes(s4.cpu().numpy(), _oracle_stokes(blk, 4, 1, 1), TOL[ctype], "one-sample IQUV", blk, ctype, 1,
+                  scale="I")
+
+
+@pytest.mark.parametrize("ctype", [lbf.F32, lbf.F16, lbf.BF16], ids=lambda c: CT_NAMES[c])
 @pytest.mark.parametrize("S,B,T,t_int", [(40, 150, 200, 8), (64, 300, 96, 16), (7, 20, 45, 1)])
 def test_complex_float_input_on_the_fast_path(ctype, S, B, T, t_int):
     # channelised (complex f32) station samples through the fast workers: one
