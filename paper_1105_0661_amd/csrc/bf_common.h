@@ -225,13 +225,24 @@ template <> struct Conv2<XT_CI8, CT_F16> {
     }
 };
 
-// complex int16 -> f16 (exact for |x| <= 2048, round-to-nearest-even beyond)
+// complex int16 -> f16 (exact for |x| <= 2048, round-to-nearest-even beyond).
+// The two halves of a word convert in place: the second conversion writes
+// the high half and keeps the low one (SDWA), so no packing instruction
+// follows -- two vector instructions per complex value instead of three.
+LBF_INLINE uint32_t cvt_i16x2_f16x2(uint32_t w) {
+    uint32_t r;
+    __asm__("v_cvt_f16_i16_sdwa %0, %1 dst_sel:WORD_0 dst_unused:UNUSED_PAD src0_sel:WORD_0\n\t"
+            "v_cvt_f16_i16_sdwa %0, %1 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1"
+            : "=&v"(r)
+            : "v"(w));
+    return r;
+}
 template <> struct Conv2<XT_CI16, CT_F16> {
     LBF_INLINE static void xy(shortx4 v, uint32_t& fx, uint32_t& fy) {
-        const halfx2 hx = {(_Float16)v[0], (_Float16)v[1]};
-        const halfx2 hy = {(_Float16)v[2], (_Float16)v[3]};
-        fx = __builtin_bit_cast(uint32_t, hx);
-        fy = __builtin_bit_cast(uint32_t, hy);
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 w = __builtin_bit_cast(u32x2, v);
+        fx = cvt_i16x2_f16x2(w[0]);
+        fy = cvt_i16x2_f16x2(w[1]);
     }
 };
 
