@@ -162,14 +162,15 @@ template <> struct Conv<XT_CI16, CT_F16> {
     }
 };
 
-// bf16 of finite station samples, round-to-nearest-even without a NaN
-// branch (integer samples are never NaN).  int8 values are exact in bf16, so
-// their float bits can simply be truncated.
-LBF_INLINE uint32_t bf16_rne_finite(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+// Two floats to a word of two bf16 (lo first), rounded to nearest even by
+// the hardware's packed conversion (v_cvt_pk_bf16_f32): one instruction per
+// pair.  int8 values are exact in bf16, so their float bits can simply be
+// truncated (pack_bf16_exact).
+LBF_INLINE uint32_t pack_bf16(float lo, float hi) {
+    typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+    const bf16x2_t r = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, r);
 }
-LBF_INLINE uint32_t pack_bf16(float lo, float hi) { return bf16_rne_finite(lo) | (bf16_rne_finite(hi) << 16); }
 LBF_INLINE uint32_t pack_bf16_exact(float lo, float hi) {
     return __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x07060302u);
 }
