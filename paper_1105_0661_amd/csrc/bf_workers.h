@@ -81,6 +81,10 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
     const int T2 = PR == PR_VOLT ? T : T / TI;
     const __amdgpu_buffer_rsrc_t ors = channel_rsrc(d, c, out_channel_bytes(d, PR, T2));
     const int trow = tile_row_sample(r);
+    // weights read one quad of stations ahead (8 more registers): where they
+    // fit without spills -- not with complex float samples (16-byte ring
+    // entries) nor beside the 16 output sums of unintegrated Stokes
+    constexpr bool PF = XT != XT_CF32 && (PR == PR_VOLT || TI >= 2);
 
     stage_weights_f32_planes(pl, d, c, b0);
     __syncthreads();
@@ -131,6 +135,13 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
         for (int o = 0; o < NOUT; ++o)
 #pragma unroll
             for (int q = 0; q < 4; ++q) sm[o][q] = 0.f;
+        // weights of the first 4 stations; with PF each later quad's are read
+        // one quad ahead, so that the LDS latency passes under 16 MFMAs
+        floatx4 br, bi;
+        if constexpr (PF) {
+            br = *reinterpret_cast<const floatx4*>(pl + wro);
+            bi = *reinterpret_cast<const floatx4*>(pl + wio);
+        }
 #pragma unroll
         for (int gi = 0; gi < 8; ++gi) {
             if (gi < ngrp) {                                   // uniform
@@ -144,9 +155,17 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
 #pragma unroll
                     for (int i = 0; i < 4; ++i) R::half(ring[gi & 1][4 * i4 + i], hsh, ax[i], ay[i]);
                     load_quad(gi & 1, i4, k * ngrp + gi + 2);
-                    __builtin_amdgcn_sched_barrier(0);
-                    const floatx4 br = *reinterpret_cast<const floatx4*>(pl + wro + s4);
-                    const floatx4 bi = *reinterpret_cast<const floatx4*>(pl + wio + s4);
+                    floatx4 nbr, nbi;
+                    if constexpr (PF) {
+                        const int s4n = s4 + 4 < 8 * ngrp ? s4 + 4 : s4;    // the last quad reads itself again
+                        nbr = *reinterpret_cast<const floatx4*>(pl + wro + s4n);
+                        nbi = *reinterpret_cast<const floatx4*>(pl + wio + s4n);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);                     // those reads issue before the MFMAs
+                    if constexpr (!PF) {
+                        br = *reinterpret_cast<const floatx4*>(pl + wro + s4);
+                        bi = *reinterpret_cast<const floatx4*>(pl + wio + s4);
+                    }
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const bool first = gi == 0 && i4 == 0 && i == 0;
@@ -154,6 +173,10 @@ LBF_INLINE void item_f32_fast(const BlockDesc& d, int item, int nbg, float* pl) 
                         acc[1] = mfma_f32(ax[i], bi[i], first ? zero16() : acc[1]);
                         acc[2] = mfma_f32(ay[i], br[i], first ? zero16() : acc[2]);
                         acc[3] = mfma_f32(ay[i], bi[i], first ? zero16() : acc[3]);
+                    }
+                    if constexpr (PF) {
+                        br = nbr;
+                        bi = nbi;
                     }
                 }
             }
