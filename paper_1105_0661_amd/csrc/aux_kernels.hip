@@ -108,9 +108,14 @@ __global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__
             v.y = (float)wi;
             reinterpret_cast<float2*>(w)[i] = v;
         } else if (WT == CT_F16) {
-            reinterpret_cast<uint32_t*>(w)[i] = pack16(f64_to_f16_bits(wr), f64_to_f16_bits(wi));
+            // round-to-odd to f32, then the packed hardware conversion (RNE)
+            typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+            const h2 v = {(_Float16)f64_to_f32_round_odd(wr), (_Float16)f64_to_f32_round_odd(wi)};
+            reinterpret_cast<uint32_t*>(w)[i] = __builtin_bit_cast(uint32_t, v);
         } else {
-            reinterpret_cast<uint32_t*>(w)[i] = pack16(f64_to_bf16_bits(wr), f64_to_bf16_bits(wi));
+            typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+            const b2 v = {(__bf16)f64_to_f32_round_odd(wr), (__bf16)f64_to_f32_round_odd(wi)};
+            reinterpret_cast<uint32_t*>(w)[i] = __builtin_bit_cast(uint32_t, v);
         }
     }
 }

@@ -80,9 +80,10 @@ template <> struct Sample<XT_CF32> {
 };
 
 // ---------------------------------------------------------------------------
-// FP64 -> narrow conversions with a single round-to-nearest-even.
-// Going through float with round-to-odd keeps one rounding: float carries
-// 24 significand bits, at least 2 more than f16 (11) or bf16 (8).
+// FP64 -> narrow conversions with a single round-to-nearest-even: round to
+// odd into float, then the hardware's RNE conversion to f16 or bf16.  Going
+// through float with round-to-odd keeps one rounding: float carries 24
+// significand bits, at least 2 more than f16 (11) or bf16 (8).
 // ---------------------------------------------------------------------------
 // Round-to-odd from the round-to-nearest result f: when d is not exact in
 // float it lies strictly between two neighbouring floats, one of them odd
@@ -96,36 +97,6 @@ __device__ inline float f64_to_f32_round_odd(double d) {
     const uint32_t toward_zero = __builtin_fabs((double)f) > __builtin_fabs(d) ? 0xffffffffu : 1u;
     return __uint_as_float(step ? u + toward_zero : u);
 }
-
-__device__ inline uint16_t f32_to_bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // NaN stays NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ inline uint16_t f64_to_f16_bits(double d) {
-    _Float16 h = (_Float16)f64_to_f32_round_odd(d);
-    return __builtin_bit_cast(uint16_t, h);
-}
-
-__device__ inline uint16_t f64_to_bf16_bits(double d) {
-    return f32_to_bf16_bits(f64_to_f32_round_odd(d));
-}
-
-__device__ inline uint16_t f32_to_f16_bits(float f) {
-    _Float16 h = (_Float16)f;
-    return __builtin_bit_cast(uint16_t, h);
-}
-
-// pack two 16-bit values into one 32-bit word (lo first in memory)
-__device__ inline uint32_t pack16(uint16_t lo, uint16_t hi) {
-    return (uint32_t)lo | ((uint32_t)hi << 16);
-}
-
-template <int CT> __device__ inline uint16_t f32_to_bits(float f);
-template <> __device__ inline uint16_t f32_to_bits<CT_F16>(float f) { return f32_to_f16_bits(f); }
-template <> __device__ inline uint16_t f32_to_bits<CT_BF16>(float f) { return f32_to_bf16_bits(f); }
 
 // ---------------------------------------------------------------------------
 // Sample-to-row map inside a 32-sample MFMA tile.  The 32x32 result of a
