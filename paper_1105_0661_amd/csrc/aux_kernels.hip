@@ -369,7 +369,10 @@ hipError_t launch_transpose(const void* in, int C2, int B, int T2, int K, int el
 // run starts on a 128-byte line.  The order in which the grid walks the tiles
 // (`walk`) is the one measured fastest for the row alignment: 0 m, channel
 // tile, beam tile (any M); 1 channel tile, m, beam tile (128-byte-aligned
-// rows); 2 beam tile, channel tile, m (other rows).
+// rows); 2 beam tile, channel tile, m (other rows).  The 16-byte accesses are
+// non-temporal: the staging is read once and the output not again here
+// (timed alone: 0.322 against 0.338 ms for 0.8 GB of Stokes, 1.222 against
+// 1.252 ms for 3 GB).
 // ---------------------------------------------------------------------------
 template <bool VEC>
 __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* __restrict__ in, int C2, int M, int B,
@@ -389,11 +392,11 @@ __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* _
         if (c >= C2) continue;
         const float* src = in + ((size_t)c * M + m) * ldb + b;
         if (VEC && b + 3 < B) {
-            const float4 v = *reinterpret_cast<const float4*>(src);
-            tile[r][4 * q + 0] = v.x;
-            tile[r][4 * q + 1] = v.y;
-            tile[r][4 * q + 2] = v.z;
-            tile[r][4 * q + 3] = v.w;
+            const floatx4 v = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(src));
+            tile[r][4 * q + 0] = v[0];
+            tile[r][4 * q + 1] = v[1];
+            tile[r][4 * q + 2] = v[2];
+            tile[r][4 * q + 3] = v[3];
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
@@ -407,12 +410,12 @@ __global__ __launch_bounds__(256) void stage_to_beam_major_kernel(const float* _
         if (b >= B) continue;
         float* dst = out + ((size_t)b * M + m) * ldo + c;
         if (VEC && c + 3 < C2) {
-            float4 v;
-            v.x = tile[4 * q + 0][rb];
-            v.y = tile[4 * q + 1][rb];
-            v.z = tile[4 * q + 2][rb];
-            v.w = tile[4 * q + 3][rb];
-            *reinterpret_cast<float4*>(dst) = v;
+            floatx4 v;
+            v[0] = tile[4 * q + 0][rb];
+            v[1] = tile[4 * q + 1][rb];
+            v[2] = tile[4 * q + 2][rb];
+            v[3] = tile[4 * q + 3][rb];
+            __builtin_nontemporal_store(v, reinterpret_cast<floatx4*>(dst));
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
