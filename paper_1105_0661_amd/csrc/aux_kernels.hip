@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void reorder_final_vec_kernel(const E* __restr
         const int r = p * RPP + rr, c = c0 + r;
         const long q = q0 + V * l;
         if (c < C2 && q < Q) {
-            const floatx4 v = *reinterpret_cast<const floatx4*>(in + ((size_t)c * B + b) * Q + q);
+            const floatx4 v = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(in + ((size_t)c * B + b) * Q + q));
             const E* e = reinterpret_cast<const E*>(&v);
 #pragma unroll
             for (int i = 0; i < V; ++i) tile[r][V * l + i] = e[i];
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void reorder_final_vec_kernel(const E* __restr
             E* e = reinterpret_cast<E*>(&v);
 #pragma unroll
             for (int i = 0; i < V; ++i) e[i] = tile[V * l + i][r];
-            *reinterpret_cast<floatx4*>(out + (((size_t)b * K + k) * T2 + t) * C2 + c) = v;
+            __builtin_nontemporal_store(v, reinterpret_cast<floatx4*>(out + (((size_t)b * K + k) * T2 + t) * C2 + c));
         }
     }
 }
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) void stage_sum_to_beam_major_kernel(const floa
         if (c >= C2) continue;
         const float* src = in + ((size_t)c * M + m) * ldb + b;
         if (VEC && b + 3 < B) {
-            const floatx4 v = *reinterpret_cast<const floatx4*>(src);
+            const floatx4 v = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(src));
 #pragma unroll
             for (int e = 0; e < 4; ++e) tile[r][4 * q + e] = v[e];
         } else {
@@ -511,13 +511,13 @@ __global__ __launch_bounds__(256) void stage_sum_channels_kernel(const float* __
         const float* src = in + ((size_t)co * F * M + m) * ldb;
         float* dst = out + (co * M + m) * (size_t)B;
         if (VEC) {
-            floatx4 sum = *reinterpret_cast<const floatx4*>(src + 4 * bv);
+            floatx4 sum = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(src + 4 * bv));
             for (int j = 1; j < F; ++j) {
-                const floatx4 v = *reinterpret_cast<const floatx4*>(src + (size_t)j * M * ldb + 4 * bv);
+                const floatx4 v = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(src + (size_t)j * M * ldb + 4 * bv));
 #pragma unroll
                 for (int e = 0; e < 4; ++e) sum[e] += v[e];
             }
-            *reinterpret_cast<floatx4*>(dst + 4 * bv) = sum;
+            __builtin_nontemporal_store(sum, reinterpret_cast<floatx4*>(dst + 4 * bv));
         } else {
             float sum = src[bv];
             for (int j = 1; j < F; ++j) sum += src[(size_t)j * M * ldb + bv];
